@@ -1,0 +1,212 @@
+/*
+ * dfpr.h -- Dynamic Frontier PageRank on MI355X (gfx950), C ABI.
+ *
+ * Method: "Lock-Free Computation of PageRank in Dynamic Graphs"
+ * (arXiv 2407.19562).  After a batch of edge deletions and insertions
+ * (Section 3.4), the ranks of the previous graph are updated by the Dynamic
+ * Frontier approach (Section 4.1): the out-neighbours of every batch source
+ * in the previous and current graph are marked affected, affected vertices
+ * are recomputed with Eq. 1 (Section 3.1) pulling over their in-edges, a
+ * vertex whose rank moves by more than the frontier tolerance marks its
+ * out-neighbours (Section 4.1.1), and the loop ends when the L-infinity
+ * change is within the iteration tolerance (Algorithms 1 and 2).
+ *
+ * Conventions shared by every entry point:
+ *  - Status: 0 is success; negative values are errors (DFPR_E*), and
+ *    DFPR_NOTCONVERGED (> 0) is a warning: ranks are valid but the sweep cap
+ *    was reached.  Nothing crosses the ABI as an exception.
+ *    dfpr_last_error() returns a message for the last failure on the
+ *    calling thread.
+ *  - Memory: every array argument is a plain pointer with an explicit
+ *    element count; `mem` says whether it is host memory (DFPR_MEM_HOST) or
+ *    device memory on the graph's device (DFPR_MEM_DEVICE).  Inputs are only
+ *    read, and are no longer needed once the call returns.  Outputs are
+ *    written by the call and complete when it returns.
+ *  - Ownership: the library owns every buffer of a graph (adjacency, ranks,
+ *    flags, worklist, counters).  The caller owns its own arrays.
+ *  - Streams: every device operation of a graph is ordered on the stream
+ *    given at creation (a hipStream_t passed as void*; NULL is the null
+ *    stream).  A call returns after its work on that stream has finished.
+ *    One graph must not be used from two threads at once; distinct graphs
+ *    are independent.
+ *  - Vertex ids are int32 in [0, n); n is fixed for the life of a graph
+ *    (no vertex insertion or deletion, Section 3.4).
+ *  - Every vertex carries an implicit self-loop (dead-end removal,
+ *    Section 5.1.3): |out(u)| counts it, and a batch edge (v, v) is ignored.
+ */
+#ifndef DFPR_H
+#define DFPR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define DFPR_OK 0
+#define DFPR_NOTCONVERGED 1 /* sweep cap reached; ranks valid              */
+#define DFPR_EINVAL (-1)    /* bad argument: null pointer, id outside [0,n),
+                               n <= 0, alpha outside (0,1), tol <= 0, ...  */
+#define DFPR_ENOMEM (-2)    /* device allocation failed; graph unchanged   */
+#define DFPR_EHIP (-3)      /* HIP runtime error; destroy the graph        */
+#define DFPR_EABORT (-4)    /* watchdog fired inside a kernel               */
+#define DFPR_ESTATE (-5)    /* call not valid in the graph's current state */
+
+/* where an array argument lives */
+#define DFPR_MEM_HOST 0
+#define DFPR_MEM_DEVICE 1
+
+/* scheduling of the rank iteration */
+#define DFPR_ASYNC 0 /* one persistent launch; in-place (Gauss-Seidel-like)
+                        ranks, per-vertex converged flags, no grid barrier
+                        (the lock-free variant, Algorithm 2)             */
+#define DFPR_SYNC 1  /* one launch per iteration; two rank vectors and an
+                        L-infinity norm per iteration (the barrier-based
+                        variant, Algorithm 1)                             */
+
+/* adjacency directions for dfpr_read_edges */
+#define DFPR_OUT 0
+#define DFPR_IN 1
+
+typedef struct dfpr_graph dfpr_graph; /* opaque */
+
+typedef struct {
+  double alpha;          /* damping factor (Section 5.1.2: 0.85)            */
+  double tol;            /* iteration tolerance tau, L-infinity (1e-10)     */
+  double frontier_tol;   /* frontier tolerance tau_f (Section 4.4: tau/1000)*/
+  int32_t max_iters;     /* cap on sweeps / iterations (500)                */
+  int32_t precision;     /* 64: fp64 ranks; 32: fp32 ranks and sums with fp64
+                            change tests and norms                          */
+  int32_t mode;          /* DFPR_ASYNC or DFPR_SYNC                         */
+  int32_t kahan_min_degree; /* fp32: compensated sums for in-degree >= this */
+  int32_t wave_min_degree;  /* in-degree at or above which a whole wavefront
+                               gathers one vertex (else one lane each)      */
+  int32_t chunk;         /* worklist positions per dynamic grab (mult. of 64)*/
+  int32_t block_size;    /* threads per workgroup (multiple of 64, <= 1024) */
+  int32_t dense_div;     /* a sweep walks the whole vertex range instead of
+                            the worklist once affected > n / dense_div
+                            (0: never)                                      */
+  int32_t renormalize;   /* fp32: rescale ranks to sum 1 (fp64 sum) after
+                            each update                                     */
+  int32_t timeout_ms;    /* watchdog for the persistent kernel (0: none)    */
+  int32_t grid_blocks;   /* persistent grid size; 0 = from occupancy        */
+} dfpr_params;
+
+typedef struct {
+  int32_t sweeps;        /* iterations (sync) or sweeps (async) performed   */
+  int32_t converged;     /* 1 if the tolerance was met before the cap       */
+  int64_t initial_marked;     /* vertices affected by the initial marking   */
+  int64_t affected;           /* vertices affected at the end               */
+  int64_t vertices_processed; /* rank recomputations, summed over sweeps    */
+  int64_t edges_gathered;     /* in-edges read by the gathers, the implicit
+                                 self-loop included                         */
+  int64_t out_edges_scanned;  /* out-edges read by frontier expansion       */
+  double max_delta;      /* sync: L-infinity change of the last iteration;
+                            async: -1 (not tracked)                         */
+  float ms;              /* device time of the call (HIP events)            */
+  float ms_kernel;       /* device time of the rank iteration alone         */
+} dfpr_stats;
+
+/* Fills `p` with the paper's defaults (alpha 0.85, tol 1e-10,
+ * frontier_tol tol/1000, 500 iterations, fp64, async) and this library's
+ * launch defaults.  Returns DFPR_EINVAL if p is NULL. */
+int dfpr_params_default(dfpr_params *p);
+
+/* Builds a graph on the current HIP device from n vertices and m edges
+ * (src[i] -> dst[i]).  Duplicate edges and self pairs in the input are
+ * dropped (edges form a set).  Ranks start at 1/n.  `params` may be NULL
+ * (defaults).  On success *out receives the handle.  Errors: DFPR_EINVAL
+ * (n <= 0, m < 0, null pointers with m > 0, an id outside [0, n), bad
+ * params), DFPR_ENOMEM, DFPR_EHIP. */
+int dfpr_graph_create(int32_t n, int64_t m, const int32_t *src,
+                      const int32_t *dst, int mem, const dfpr_params *params,
+                      void *hip_stream, dfpr_graph **out);
+
+/* Frees every device buffer of the graph.  NULL is accepted. */
+int dfpr_graph_destroy(dfpr_graph *g);
+
+/* Replaces / reads the graph's parameters.  Validated like create. */
+int dfpr_set_params(dfpr_graph *g, const dfpr_params *p);
+int dfpr_get_params(const dfpr_graph *g, dfpr_params *p);
+
+/* Number of vertices and of stored edges (self-loops not counted). */
+int dfpr_graph_size(const dfpr_graph *g, int32_t *n, int64_t *m);
+
+/* Static PageRank (Eq. 1; Algorithm 3): ranks restart at 1/n and Jacobi
+ * iterations over every vertex run until the L-infinity change is <= tol or
+ * max_iters.  Pending marks are kept.  Returns DFPR_NOTCONVERGED at the
+ * cap.  `stats` may be NULL. */
+int dfpr_static(dfpr_graph *g, dfpr_stats *stats);
+
+/* Naive-dynamic PageRank (Section 3.5.1): the same iteration over every
+ * vertex, started from the current ranks. */
+int dfpr_naive_dynamic(dfpr_graph *g, dfpr_stats *stats);
+
+/* Overwrites the ranks with r[n] (fp64; rounded for fp32 graphs). */
+int dfpr_set_ranks(dfpr_graph *g, const double *r, int mem);
+
+/* Copies the ranks to out[n] as fp64. */
+int dfpr_read_ranks(const dfpr_graph *g, double *out, int mem);
+
+/* Applies one batch (Section 3.4) in place to both the out- and the
+ * in-adjacency: first every deletion (del_src[i] -> del_dst[i]), then every
+ * insertion, with set semantics (deleting an absent edge or inserting a
+ * present one changes nothing; self pairs are ignored; duplicates count
+ * once).  The whole batch is validated before anything changes (all or
+ * nothing on DFPR_EINVAL).  The sources of the edges that really changed
+ * are marked for the next dfpr_update (Algorithm 1/2 initial marking: the
+ * out-neighbours of u in the previous and the current graph, u itself
+ * through its self-loop); several batches may be applied before one
+ * update.  applied_del / applied_ins (may be NULL) receive the number of
+ * edges actually deleted / inserted.  Errors: DFPR_EINVAL, DFPR_ENOMEM
+ * (graph unchanged), DFPR_EHIP. */
+int dfpr_apply_batch(dfpr_graph *g, int64_t n_del, const int32_t *del_src,
+                     const int32_t *del_dst, int64_t n_ins,
+                     const int32_t *ins_src, const int32_t *ins_dst, int mem,
+                     int64_t *applied_del, int64_t *applied_ins);
+
+/* Dynamic Frontier update (Section 4; Algorithm 1 in DFPR_SYNC mode,
+ * Algorithm 2's lock-free scheme in DFPR_ASYNC mode) from the current ranks
+ * over the vertices marked since the last update; consumes the marks.
+ * Returns DFPR_OK, DFPR_NOTCONVERGED, DFPR_EABORT (watchdog), DFPR_EHIP.
+ * `stats` may be NULL. */
+int dfpr_update(dfpr_graph *g, dfpr_stats *stats);
+
+/* Dynamic Frontier updates of `count` graphs in one persistent launch
+ * (async scheduling only; all graphs on the same device, the first graph's
+ * stream is used).  stats[count] may be NULL.  Returns the worst status. */
+int dfpr_update_many(dfpr_graph *const *gs, int32_t count, dfpr_stats *stats);
+
+/* Copies the stored edges (self-loops excluded) of one direction to host
+ * arrays src[cap], dst[cap] (row order unspecified); *count receives the
+ * edge count.  DFPR_EINVAL if cap is too small. */
+int dfpr_read_edges(const dfpr_graph *g, int dir, int32_t *src, int32_t *dst,
+                    int64_t cap, int64_t *count);
+
+/* Affected flags after the marking / last update (1 byte per vertex) and
+ * the number of vertices currently marked; for tests. */
+int dfpr_read_marks(const dfpr_graph *g, uint8_t *affected, int64_t *count);
+
+/* Device bytes held by the graph. */
+int dfpr_graph_bytes(const dfpr_graph *g, int64_t *bytes);
+
+/* Copies `bytes` bytes from src to dst (device pointers) with a streaming
+ * kernel on `hip_stream`; *ms receives its device time.  Used to measure
+ * the achievable HBM bandwidth next to the rank kernels. */
+int dfpr_stream_copy(void *dst, const void *src, int64_t bytes,
+                     void *hip_stream, float *ms);
+
+/* Name of the last kernel that dominates dfpr_update / dfpr_static, and
+ * its algorithmic byte count for the last call (see the design notes for
+ * the per-unit figures): one entry per launch of the rank iteration. */
+int dfpr_last_kernel_bytes(const dfpr_graph *g, double *bytes,
+                           int32_t *launches);
+
+const char *dfpr_strerror(int status);
+const char *dfpr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DFPR_H */

@@ -1,0 +1,487 @@
+// In-place batch update of the slack CSR (Section 3.4) and the initial
+// marking of the Dynamic Frontier approach (Section 4.1.1; Algorithms 1
+// and 2, before the iterations).
+//
+// Per direction the batch becomes 64-bit keys row << 32 | other << 1 | ins
+// (ins = 0 deletion, 1 insertion), radix-sorted and de-duplicated, so each
+// touched row owns one contiguous segment, sorted by the other endpoint with
+// a deletion ahead of an insertion of the same pair.  One wavefront edits one
+// row:
+//   deletions: every row entry is looked up (binary search) among the
+//     segment's deletions and the survivors are compacted in place
+//     (ballot + popcount prefix), O(deg log k) per row whatever k is;
+//   insertions: row entries are looked up among the segment's insertions to
+//     drop those already present, then the new ones are appended; a row that
+//     would outgrow its slots first moves to the spare tail of the adjacency
+//     array (atomic bump pointer).  When the spare tail runs out the host
+//     grows the array and re-runs the rows left pending.
+// Marking: for every source u with a real change, u itself (self-loop), its
+// current out-neighbours and the targets of its deleted edges -- together
+// (G^{t-1} union G^t).out(u) -- get the affected and not-converged flags,
+// and newly affected vertices are appended to the worklist.
+#include <cstring>
+
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
+
+#include "dfpr_common.h"
+
+namespace dfpr {
+
+namespace {
+
+constexpr unsigned long long kNoKey = ~0ull;
+constexpr uint8_t kApplied = 1, kExists = 2;
+
+inline int grid_for(int64_t work, int cu) {
+  int64_t b = (work + 255) / 256;
+  const int64_t lim = (int64_t)cu * 16;
+  if (b > lim) b = lim;
+  return (int)(b < 1 ? 1 : b);
+}
+
+__global__ void k_validate2(int64_t m1, const int32_t *a1, const int32_t *b1,
+                            int64_t m2, const int32_t *a2, const int32_t *b2,
+                            int32_t n, Ctl *ctl) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m1 + m2;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t x = i < m1 ? a1[i] : a2[i - m1];
+    const int32_t y = i < m1 ? b1[i] : b2[i - m1];
+    if (x < 0 || x >= n || y < 0 || y >= n) atomicOr(&ctl->invalid, 1);
+  }
+}
+
+// dir 0: rows are sources (out), dir 1: rows are targets (in)
+__global__ void k_batch_keys(int dir, int64_t nd, const int32_t *ds,
+                             const int32_t *dd, int64_t ni, const int32_t *is,
+                             const int32_t *id, unsigned long long *keys) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nd + ni;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const bool ins = i >= nd;
+    const uint32_t u = (uint32_t)(ins ? is[i - nd] : ds[i]);
+    const uint32_t v = (uint32_t)(ins ? id[i - nd] : dd[i]);
+    const uint32_t row = dir == 0 ? u : v, oth = dir == 0 ? v : u;
+    keys[i] = u == v ? kNoKey
+                     : ((unsigned long long)row << 32 |
+                        (unsigned long long)oth << 1 | (ins ? 1u : 0u));
+  }
+}
+
+// head: first copy of a key; seg: first key of a row
+__global__ void k_batch_heads(int64_t m, const unsigned long long *k,
+                              int64_t *head, int64_t *seg) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const unsigned long long x = k[i];
+    const bool h = x != kNoKey && (i == 0 || k[i - 1] != x);
+    const bool s = x != kNoKey && (i == 0 || (k[i - 1] >> 32) != (x >> 32));
+    head[i] = h;
+    seg[i] = s;
+  }
+}
+
+__global__ void k_batch_compact(int64_t m, const unsigned long long *k,
+                                const int64_t *hrank, const int64_t *srank,
+                                unsigned long long *uk, int64_t *segstart) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const unsigned long long x = k[i];
+    const bool h = x != kNoKey && (i == 0 || k[i - 1] != x);
+    const bool s = x != kNoKey && (i == 0 || (k[i - 1] >> 32) != (x >> 32));
+    if (h) uk[hrank[i]] = x;
+    if (s) segstart[srank[i]] = hrank[i];
+  }
+}
+
+__global__ void k_set_i64(int64_t *p, int64_t v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+__device__ __forceinline__ int64_t find_key(const unsigned long long *uk,
+                                            int64_t a, int64_t b,
+                                            unsigned long long key) {
+  int64_t lo = a, hi = b;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (uk[mid] < key)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return (lo < b && uk[lo] == key) ? lo : -1;
+}
+
+struct AdjView {
+  int64_t *off;
+  int32_t *deg;
+  int32_t *cap;
+  int32_t *adj;
+  int64_t adj_cap;
+};
+
+__global__ void k_apply_delete(int64_t S, const int64_t *segstart,
+                               const unsigned long long *uk, uint8_t *status,
+                               AdjView A) {
+  const int lane = lane_id();
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t s = wave; s < S; s += nwaves) {
+    const int64_t a = segstart[s], b = segstart[s + 1];
+    bool has_del = false;
+    for (int64_t i = a; i < b && !has_del; i += kWave) {
+      const bool d = i + lane < b && (uk[i + lane] & 1ull) == 0;
+      has_del = __ballot(d) != 0;
+    }
+    if (!has_del) continue;
+    const uint32_t row = (uint32_t)(uk[a] >> 32);
+    const int64_t off = A.off[row];
+    const int32_t deg = A.deg[row];
+    int32_t w = 0;
+    for (int32_t t = 0; t < deg; t += kWave) {
+      const int32_t idx = t + lane;
+      int32_t x = -1;
+      bool keep = false;
+      if (idx < deg) {
+        x = A.adj[off + idx];
+        const int64_t j = find_key(uk, a, b,
+                                   (unsigned long long)row << 32 |
+                                       (unsigned long long)(uint32_t)x << 1);
+        if (j >= 0) status[j] |= kApplied;
+        keep = j < 0;
+      }
+      const uint64_t mask = __ballot(keep);
+      if (keep) A.adj[off + w + __popcll(mask & lanemask_lt())] = x;
+      w += __popcll(mask);
+    }
+    if (lane == 0) A.deg[row] = w;
+  }
+}
+
+__global__ void k_apply_insert(int64_t S, const int64_t *segstart,
+                               const unsigned long long *uk, uint8_t *status,
+                               uint8_t *done, AdjView A,
+                               unsigned long long *used, int *overflow) {
+  const int lane = lane_id();
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t s = wave; s < S; s += nwaves) {
+    if (done[s]) continue;
+    const int64_t a = segstart[s], b = segstart[s + 1];
+    const uint32_t row = (uint32_t)(uk[a] >> 32);
+    int64_t off = A.off[row];
+    const int32_t deg = A.deg[row];
+    // drop insertions of edges already present
+    int n_ins = 0;
+    for (int64_t i = a; i < b; i += kWave)
+      n_ins += __popcll(__ballot(i + lane < b && (uk[i + lane] & 1ull)));
+    if (n_ins == 0) {
+      if (lane == 0) done[s] = 1;
+      continue;
+    }
+    for (int32_t t = 0; t < deg; t += kWave) {
+      const int32_t idx = t + lane;
+      if (idx < deg) {
+        const int32_t x = A.adj[off + idx];
+        const int64_t j = find_key(uk, a, b,
+                                   (unsigned long long)row << 32 |
+                                       (unsigned long long)(uint32_t)x << 1 | 1ull);
+        if (j >= 0) status[j] |= kExists;
+      }
+    }
+    int k_new = 0;
+    for (int64_t i = a; i < b; i += kWave) {
+      const int64_t e = i + lane;
+      const bool c = e < b && (uk[e] & 1ull) && !(status[e] & kExists);
+      k_new += __popcll(__ballot(c));
+    }
+    if (k_new == 0) {
+      if (lane == 0) done[s] = 1;
+      continue;
+    }
+    const int32_t cap = A.cap[row];
+    if (deg + k_new > cap) {
+      int64_t need = 2 * ((int64_t)deg + k_new);
+      if (need < 8) need = 8;
+      need = (need + 3) & ~3ll;
+      unsigned long long p = 0;
+      if (lane == 0)
+        p = __hip_atomic_fetch_add(used, (unsigned long long)need,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      p = __shfl(p, 0);
+      if ((int64_t)p + need > A.adj_cap) {
+        if (lane == 0) atomicOr(overflow, 1);
+        continue;  // left pending; the host grows the array and re-runs
+      }
+      for (int32_t t = lane; t < deg; t += kWave) A.adj[p + t] = A.adj[off + t];
+      off = (int64_t)p;
+      if (lane == 0) {
+        A.off[row] = off;
+        A.cap[row] = (int32_t)need;
+      }
+    }
+    int32_t w = deg;
+    for (int64_t i = a; i < b; i += kWave) {
+      const int64_t e = i + lane;
+      const bool c = e < b && (uk[e] & 1ull) && !(status[e] & kExists);
+      const uint64_t mask = __ballot(c);
+      if (c) {
+        A.adj[off + w + __popcll(mask & lanemask_lt())] =
+            (int32_t)((uk[e] >> 1) & 0x7FFFFFFFull);
+        status[e] |= kApplied;
+      }
+      w += __popcll(mask);
+    }
+    if (lane == 0) {
+      A.deg[row] = w;
+      done[s] = 1;
+    }
+  }
+}
+
+__global__ void k_count_applied(int64_t U, const unsigned long long *uk,
+                                const uint8_t *status,
+                                unsigned long long *del_cnt,
+                                unsigned long long *ins_cnt) {
+  unsigned long long d = 0, in = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < U;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (status[i] & kApplied) {
+      if (uk[i] & 1ull)
+        ++in;
+      else
+        ++d;
+    }
+  }
+  d = wave_sum(d);
+  in = wave_sum(in);
+  if (lane_id() == 0) {
+    if (d) atomicAdd(del_cnt, d);
+    if (in) atomicAdd(ins_cnt, in);
+  }
+}
+
+// Marks (G^{t-1} U G^t).out(u) for every source u with a real change.
+template <typename T>
+__global__ void k_mark_sources(int64_t S, const int64_t *segstart,
+                               const unsigned long long *uk,
+                               const uint8_t *status, AdjView out,
+                               const T *R, T *C, uint32_t *flags, int32_t *wl,
+                               Ctl *ctl) {
+  const int lane = lane_id();
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  long long nc = 0, appended = 0;
+  for (int64_t s = wave; s < S; s += nwaves) {
+    const int64_t a = segstart[s], b = segstart[s + 1];
+    bool any = false;
+    for (int64_t i = a; i < b && !any; i += kWave)
+      any = __ballot(i + lane < b && (status[i + lane] & kApplied)) != 0;
+    if (!any) continue;
+    const int32_t u = (int32_t)(uk[a] >> 32);
+    const int64_t off = out.off[u];
+    const int32_t deg = out.deg[u];
+    if (lane == 0) C[u] = (T)((double)R[u] / (double)(deg + 1));
+    // u itself (implicit self-loop), then its current out-row
+    for (int32_t t = -1; t < deg; t += kWave) {
+      const int32_t idx = t + lane;
+      bool want = false;
+      int32_t v = -1;
+      if (idx < deg) {
+        v = idx < 0 ? u : out.adj[off + idx];
+        const uint32_t old = flag_set(flags, v, kVA | kRC);
+        want = !(old & kVA);
+        nc += !(old & kRC);
+      }
+      appended += wave_append(want, v, wl, &ctl->tail, false);
+    }
+    // targets of the deleted edges of u (they were out-neighbours in G^{t-1})
+    for (int64_t i = a; i < b; i += kWave) {
+      const int64_t e = i + lane;
+      bool want = false;
+      int32_t v = -1;
+      if (e < b && !(uk[e] & 1ull) && (status[e] & kApplied)) {
+        v = (int32_t)((uk[e] >> 1) & 0x7FFFFFFFull);
+        const uint32_t old = flag_set(flags, v, kVA | kRC);
+        want = !(old & kVA);
+        nc += !(old & kRC);
+      }
+      appended += wave_append(want, v, wl, &ctl->tail, false);
+    }
+  }
+  nc = wave_sum(nc);
+  if (lane == 0) {
+    if (nc) atomicAdd((unsigned long long *)&ctl->nc, (unsigned long long)nc);
+    if (appended) atomicAdd((unsigned long long *)&ctl->marked, (unsigned long long)appended);
+  }
+}
+
+}  // namespace
+
+// Sorts and de-duplicates the batch for one direction.  Outputs (in scratch
+// slots base..base+2): uk[U] keys, segstart[S+1], status[U] zeroed.
+static int prepare_direction(dfpr_graph *g, int dir, int64_t nd,
+                             const int32_t *ds, const int32_t *dd, int64_t ni,
+                             const int32_t *is, const int32_t *id, int base,
+                             unsigned long long **uk_out, int64_t **seg_out,
+                             uint8_t **status_out, int64_t *U_out,
+                             int64_t *S_out) {
+  hipStream_t s = g->stream;
+  const int cu = g->cu_count;
+  const int64_t m = nd + ni;
+  int rc;
+  void *ka, *kb, *hr, *sr, *tmp, *uk, *seg, *st;
+  if ((rc = scratch_get(g, 0, m * 8, &ka))) return rc;
+  if ((rc = scratch_get(g, 1, m * 8, &kb))) return rc;
+  if ((rc = scratch_get(g, 2, m * 8, &hr))) return rc;
+  if ((rc = scratch_get(g, 3, m * 8, &sr))) return rc;
+  k_batch_keys<<<grid_for(m, cu), 256, 0, s>>>(dir, nd, ds, dd, ni, is, id,
+                                               (unsigned long long *)ka);
+  size_t tb = 0;
+  DFPR_HIP(rocprim::radix_sort_keys(nullptr, tb, (unsigned long long *)ka,
+                                    (unsigned long long *)kb, (size_t)m, 0, 64, s));
+  if ((rc = scratch_get(g, 7, tb, &tmp))) return rc;
+  DFPR_HIP(rocprim::radix_sort_keys(tmp, tb, (unsigned long long *)ka,
+                                    (unsigned long long *)kb, (size_t)m, 0, 64, s));
+  k_batch_heads<<<grid_for(m, cu), 256, 0, s>>>(m, (unsigned long long *)kb,
+                                                (int64_t *)hr, (int64_t *)sr);
+  // counts: last head/seg flag + exclusive scans
+  int64_t lastf[2] = {0, 0};
+  DFPR_HIP(hipMemcpyAsync(&lastf[0], (int64_t *)hr + (m - 1), 8, hipMemcpyDeviceToHost, s));
+  DFPR_HIP(hipMemcpyAsync(&lastf[1], (int64_t *)sr + (m - 1), 8, hipMemcpyDeviceToHost, s));
+  for (int q = 0; q < 2; ++q) {
+    int64_t *arr = q == 0 ? (int64_t *)hr : (int64_t *)sr;
+    tb = 0;
+    DFPR_HIP(rocprim::exclusive_scan(nullptr, tb, arr, arr, (int64_t)0, (size_t)m,
+                                     rocprim::plus<int64_t>(), s));
+    if ((rc = scratch_get(g, 7, tb, &tmp))) return rc;
+    DFPR_HIP(rocprim::exclusive_scan(tmp, tb, arr, arr, (int64_t)0, (size_t)m,
+                                     rocprim::plus<int64_t>(), s));
+  }
+  int64_t lastr[2] = {0, 0};
+  DFPR_HIP(hipMemcpyAsync(&lastr[0], (int64_t *)hr + (m - 1), 8, hipMemcpyDeviceToHost, s));
+  DFPR_HIP(hipMemcpyAsync(&lastr[1], (int64_t *)sr + (m - 1), 8, hipMemcpyDeviceToHost, s));
+  DFPR_HIP(hipStreamSynchronize(s));
+  const int64_t U = lastr[0] + lastf[0];
+  const int64_t S = lastr[1] + lastf[1];
+  if ((rc = scratch_get(g, base, (U > 0 ? U : 1) * 8, &uk))) return rc;
+  if ((rc = scratch_get(g, base + 1, (S + 1) * 8, &seg))) return rc;
+  if ((rc = scratch_get(g, base + 2, (U > 0 ? U : 1) + (S + 1), &st))) return rc;
+  k_batch_compact<<<grid_for(m, cu), 256, 0, s>>>(m, (unsigned long long *)kb,
+                                                  (int64_t *)hr, (int64_t *)sr,
+                                                  (unsigned long long *)uk,
+                                                  (int64_t *)seg);
+  k_set_i64<<<1, 64, 0, s>>>((int64_t *)seg + S, U);
+  DFPR_HIP(hipMemsetAsync(st, 0, (U > 0 ? U : 1) + (S + 1), s));
+  DFPR_HIP(hipGetLastError());
+  *uk_out = (unsigned long long *)uk;
+  *seg_out = (int64_t *)seg;
+  *status_out = (uint8_t *)st;
+  *U_out = U;
+  *S_out = S;
+  return DFPR_OK;
+}
+
+static int grow_adj(dfpr_graph *g, int dir) {
+  Adj &A = dir == 0 ? g->out : g->in;
+  hipStream_t s = g->stream;
+  unsigned long long used = 0;
+  DFPR_HIP(hipMemcpyAsync(&used, &g->ctl->adj_used[dir], 8, hipMemcpyDeviceToHost, s));
+  DFPR_HIP(hipStreamSynchronize(s));
+  int64_t want = A.adj_cap * 2;
+  if ((int64_t)used + A.adj_cap / 2 > want) want = (int64_t)used + A.adj_cap / 2;
+  want = (want + 3) & ~3ll;
+  int32_t *na = nullptr;
+  DFPR_HIP(hipMalloc(&na, sizeof(int32_t) * want));
+  DFPR_HIP(hipMemcpyAsync(na, A.adj, sizeof(int32_t) * A.adj_cap,
+                          hipMemcpyDeviceToDevice, s));
+  DFPR_HIP(hipStreamSynchronize(s));
+  DFPR_HIP(hipFree(A.adj));
+  A.adj = na;
+  A.adj_cap = want;
+  return DFPR_OK;
+}
+
+int apply_batch(dfpr_graph *g, int64_t nd, const int32_t *ds,
+                const int32_t *dd, int64_t ni, const int32_t *is,
+                const int32_t *id, int64_t *applied_del,
+                int64_t *applied_ins) {
+  hipStream_t s = g->stream;
+  const int cu = g->cu_count;
+  const int64_t m = nd + ni;
+  DFPR_HIP(hipMemsetAsync(&g->ctl->invalid, 0, sizeof(int) * 2, s));
+  DFPR_HIP(hipMemsetAsync(&g->ctl->ins_applied, 0, sizeof(unsigned long long) * 4, s));
+  if (m == 0) {
+    if (applied_del) *applied_del = 0;
+    if (applied_ins) *applied_ins = 0;
+    return DFPR_OK;
+  }
+  k_validate2<<<grid_for(m, cu), 256, 0, s>>>(nd, ds, dd, ni, is, id, g->n, g->ctl);
+  DFPR_HIP(hipMemcpyAsync(g->h_ctl, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+  DFPR_HIP(hipStreamSynchronize(s));
+  if (g->h_ctl->invalid) return fail(DFPR_EINVAL, "batch id outside [0, n)");
+
+  unsigned long long *uk[2];
+  int64_t *seg[2];
+  uint8_t *st[2];
+  int64_t U[2], S[2];
+  // in direction first (slots 4..6 are reused by the out direction's marks)
+  for (int dir = 1; dir >= 0; --dir) {
+    const int base = 8 + 3 * dir;
+    int rc = prepare_direction(g, dir, nd, ds, dd, ni, is, id, base, &uk[dir],
+                               &seg[dir], &st[dir], &U[dir], &S[dir]);
+    if (rc) return rc;
+    Adj &A = dir == 0 ? g->out : g->in;
+    if (S[dir] == 0) continue;
+    uint8_t *done = st[dir] + (U[dir] > 0 ? U[dir] : 1);
+    const int blocks = grid_for(S[dir] * 64, cu);
+    AdjView v{A.off, A.deg, A.cap, A.adj, A.adj_cap};
+    k_apply_delete<<<blocks, 256, 0, s>>>(S[dir], seg[dir], uk[dir], st[dir], v);
+    DFPR_HIP(hipGetLastError());
+    for (int attempt = 0; attempt < 16; ++attempt) {
+      AdjView w{A.off, A.deg, A.cap, A.adj, A.adj_cap};
+      k_apply_insert<<<blocks, 256, 0, s>>>(S[dir], seg[dir], uk[dir], st[dir],
+                                            done, w, &g->ctl->adj_used[dir],
+                                            &g->ctl->overflow);
+      DFPR_HIP(hipGetLastError());
+      int ovf = 0;
+      DFPR_HIP(hipMemcpyAsync(&ovf, &g->ctl->overflow, sizeof(int), hipMemcpyDeviceToHost, s));
+      DFPR_HIP(hipStreamSynchronize(s));
+      if (!ovf) break;
+      DFPR_HIP(hipMemsetAsync(&g->ctl->overflow, 0, sizeof(int), s));
+      int rc2 = grow_adj(g, dir);
+      if (rc2) return rc2;
+      if (attempt == 15) return fail(DFPR_ENOMEM, "adjacency growth did not converge");
+    }
+    k_count_applied<<<grid_for(U[dir], cu), 256, 0, s>>>(
+        U[dir], uk[dir], st[dir],
+        dir == 0 ? &g->ctl->del_applied : &g->ctl->del_applied_in,
+        dir == 0 ? &g->ctl->ins_applied : &g->ctl->ins_applied_in);
+    DFPR_HIP(hipGetLastError());
+  }
+  // marking over the out-direction segments
+  if (S[0] > 0) {
+    const int blocks = grid_for(S[0] * 64, cu);
+    AdjView o{g->out.off, g->out.deg, g->out.cap, g->out.adj, g->out.adj_cap};
+    if (g->elem == 8)
+      k_mark_sources<double><<<blocks, 256, 0, s>>>(
+          S[0], seg[0], uk[0], st[0], o, (const double *)g->R[g->cur],
+          (double *)g->C[g->cur], g->flags, g->wl, g->ctl);
+    else
+      k_mark_sources<float><<<blocks, 256, 0, s>>>(
+          S[0], seg[0], uk[0], st[0], o, (const float *)g->R[g->cur],
+          (float *)g->C[g->cur], g->flags, g->wl, g->ctl);
+    DFPR_HIP(hipGetLastError());
+  }
+  DFPR_HIP(hipMemcpyAsync(g->h_ctl, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+  DFPR_HIP(hipStreamSynchronize(s));
+  const Ctl &h = *g->h_ctl;
+  if (h.del_applied != h.del_applied_in || h.ins_applied != h.ins_applied_in)
+    return fail(DFPR_EHIP, "in/out adjacency disagree after the batch");
+  g->m += (int64_t)h.ins_applied - (int64_t)h.del_applied;
+  g->pending_marks = (int64_t)h.tail;
+  if (applied_del) *applied_del = (int64_t)h.del_applied;
+  if (applied_ins) *applied_ins = (int64_t)h.ins_applied;
+  return DFPR_OK;
+}
+
+}  // namespace dfpr

@@ -1,0 +1,235 @@
+// Internal definitions shared by the HIP translation units of libdfpr.
+//
+// Device layout of one graph (every array in HBM, owned by the library):
+//   slack CSR per direction (out: rows are sources, in: rows are targets)
+//     off[n]  int64  first slot of the row in adj (always a multiple of 4,
+//                    so a row starts on a 16-byte boundary)
+//     deg[n]  int32  stored entries (the implicit self-loop is not stored)
+//     cap[n]  int32  slots reserved for the row (multiple of 4)
+//     adj[*]  int32  row entries; rows that outgrow their slots move to the
+//                    spare tail of the same array (bump allocation)
+//   ranks R[2][n] and contributions C[2][n] = R / (out-degree + 1), fp64 or
+//   fp32; only R[cur], C[cur] are meaningful between calls (the second
+//   buffer is the Jacobi target of synchronous iterations)
+//   flags[n] bytes: bit 0 affected (V_A), bit 1 not converged (R_C)
+//   worklist wl[n] int32 (unused slots hold -1), appended through ctl->tail
+//   Ctl: counters and the scheduling word of the persistent kernel
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/dfpr.h"
+
+namespace dfpr {
+
+constexpr int kWave = 64;
+constexpr int kMaxIters = 8000;  // sweep index field holds 13 bits
+
+// Flag bits in the per-vertex byte.
+constexpr uint32_t kVA = 1u;  // affected
+constexpr uint32_t kRC = 2u;  // rank not yet converged
+
+// Scheduling word of the persistent kernel (one 64-bit atomic):
+//   bit 63 done, bit 62 dense sweeps, bit 61 stopped at the sweep cap,
+//   bits 48..60 sweep index, bits 16..47 cursor, bits 0..15 workers that
+//   hold a chunk.
+constexpr uint64_t kDone = 1ull << 63;
+constexpr uint64_t kDense = 1ull << 62;
+constexpr uint64_t kCapped = 1ull << 61;
+constexpr int kSweepShift = 48;
+constexpr uint64_t kSweepMask = 0x1FFFull;
+constexpr int kCursorShift = 16;
+constexpr uint64_t kCursorMask = 0xFFFFFFFFull;
+constexpr uint64_t kInflightMask = 0xFFFFull;
+
+// Device control block of one graph.
+struct Ctl {
+  unsigned long long state;        // async scheduling word
+  unsigned long long tail;         // worklist length
+  long long nc;                    // vertices with R_C set
+  long long marked;                // vertices appended by the batch marking
+  unsigned long long vertices;     // stats of the running update
+  unsigned long long edges;
+  unsigned long long out_scanned;
+  unsigned long long ins_applied;  // apply_batch results (out direction)
+  unsigned long long del_applied;
+  unsigned long long ins_applied_in;  // the same seen from the in direction
+  unsigned long long del_applied_in;
+  unsigned long long adj_used[2];  // bump pointers: out, in
+  int invalid;                     // an input id was out of range
+  int overflow;                    // an adjacency array ran out of slots
+  int abort;                       // watchdog fired
+  int sync_done;                   // synchronous iteration finished
+  int sync_final;                  // iterations made by the synchronous loop
+  int pad;
+  double sum;                      // fp64 rank sum (renormalisation)
+};
+
+// One direction of the slack CSR.
+struct Adj {
+  int64_t *off = nullptr;
+  int32_t *deg = nullptr;
+  int32_t *cap = nullptr;
+  int32_t *adj = nullptr;
+  int64_t adj_cap = 0;  // slots allocated in adj
+};
+
+// Reusable device scratch of apply_batch (grown on demand).
+struct Scratch {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace dfpr
+
+struct dfpr_graph {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int32_t n = 0;
+  int64_t m = 0;  // stored edges (host mirror)
+  dfpr_params p{};
+  dfpr::Adj out, in;
+  void *R[2] = {nullptr, nullptr};
+  void *C[2] = {nullptr, nullptr};
+  int cur = 0;
+  int elem = 8;  // bytes per rank (8 fp64, 4 fp32)
+  uint32_t *flags = nullptr;
+  int32_t *wl = nullptr;
+  dfpr::Ctl *ctl = nullptr;
+  dfpr::Ctl *h_ctl = nullptr;           // pinned host mirror
+  unsigned long long *sync_max = nullptr;   // [kMaxIters] bit patterns
+  unsigned long long *sync_grab = nullptr;  // [kMaxIters] chunk tickets
+  unsigned long long *sync_len = nullptr;   // [kMaxIters] worklist snapshot
+  int64_t pending_marks = 0;  // host view of marks not yet consumed
+  dfpr::Scratch scratch[16];
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  double last_bytes = 0.0;
+  int32_t last_launches = 0;
+  int cu_count = 0;
+  int wallclock_khz = 0;
+};
+
+namespace dfpr {
+
+// Error plumbing: every entry point returns a status and records a message.
+void set_error(const std::string &msg);
+int fail(int status, const std::string &msg);
+
+#define DFPR_HIP(expr)                                                    \
+  do {                                                                    \
+    hipError_t e_ = (expr);                                               \
+    if (e_ != hipSuccess)                                                 \
+      return ::dfpr::fail(e_ == hipErrorOutOfMemory ? DFPR_ENOMEM : DFPR_EHIP, \
+                          std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// Grows scratch slot `i` of g to at least `bytes`.
+int scratch_get(dfpr_graph *g, int i, size_t bytes, void **out);
+
+// Validates params.
+int check_params(const dfpr_params *p);
+
+// Builders (dfpr_build.hip).
+int build_graph(dfpr_graph *g, int64_t m, const int32_t *src,
+                const int32_t *dst);
+
+// Ranks (dfpr_rank.hip).
+int init_uniform_ranks(dfpr_graph *g);
+int refresh_contributions(dfpr_graph *g);
+
+// Device helpers ------------------------------------------------------------
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+template <typename T>
+__device__ __forceinline__ T load_agent(const T *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void store_agent(T *p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t flag_byte(const uint32_t *flags, int32_t v,
+                                              bool coherent) {
+  uint32_t w = coherent ? load_agent(flags + (v >> 2)) : flags[v >> 2];
+  return (w >> ((v & 3) * 8)) & 0xFFu;
+}
+
+// Sets `bits` in the flag byte of v and returns the byte's previous bits.
+__device__ __forceinline__ uint32_t flag_set(uint32_t *flags, int32_t v,
+                                             uint32_t bits) {
+  const int sh = (v & 3) * 8;
+  uint32_t old = __hip_atomic_fetch_or(flags + (v >> 2), bits << sh,
+                                       __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+  return (old >> sh) & 0xFFu;
+}
+
+__device__ __forceinline__ uint32_t flag_clear(uint32_t *flags, int32_t v,
+                                               uint32_t bits) {
+  const int sh = (v & 3) * 8;
+  uint32_t old = __hip_atomic_fetch_and(flags + (v >> 2), ~(bits << sh),
+                                        __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+  return (old >> sh) & 0xFFu;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  return x;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    T y = __shfl_xor(x, o);
+    x = y > x ? y : x;
+  }
+  return x;
+}
+
+// Broadcast lane 0's 64-bit value to the wave (all lanes active).
+__device__ __forceinline__ unsigned long long bcast0(unsigned long long x) {
+  uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+  uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const int l = lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// Appends v (on lanes where `want` holds) to the worklist with one atomic
+// per wave.  All lanes of the wave must call it together.
+__device__ __forceinline__ int wave_append(bool want, int32_t v,
+                                           int32_t *wl,
+                                           unsigned long long *tail,
+                                           bool coherent) {
+  const uint64_t mask = __ballot(want);
+  if (mask == 0) return 0;
+  const int cnt = __popcll(mask);
+  const int leader = __ffsll((long long)mask) - 1;
+  unsigned long long base = 0;
+  if (lane_id() == leader)
+    base = __hip_atomic_fetch_add(tail, (unsigned long long)cnt,
+                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  base = __shfl(base, leader);
+  if (want) {
+    const unsigned long long pos = base + __popcll(mask & lanemask_lt());
+    if (coherent)
+      store_agent(wl + pos, v);
+    else
+      wl[pos] = v;
+  }
+  return cnt;
+}
+
+}  // namespace dfpr

@@ -1,0 +1,349 @@
+"""HIP path vs the CPU oracle, element by element, through the C ABI.
+
+Tolerances: fp64 ranks within 1e-9 L-infinity of the oracle's fixed point
+(the paper's DF error bound at tau = 1e-10, Sections 4.4 and 5.2.2); fp32
+ranks within 1e-6 normwise relative (max |R32 - R*| / max |R*|).  Graph
+structure (edge sets, applied counts, marks) is compared exactly.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from paper_2407_19562_amd import inputs
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+FP64_TOL = 1e-9
+FP32_REL = 1e-6
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def D():
+    import torch
+    assert torch.cuda.is_available(), "no HIP device"
+    from paper_2407_19562_amd import dfpr
+    dfpr._lib()
+    return dfpr
+
+
+@pytest.fixture(scope="module")
+def O():
+    import oracle
+    oracle._lib()
+    return oracle
+
+
+def edge_keys(n, s, d):
+    return np.sort(s.astype(np.int64) * n + d.astype(np.int64))
+
+
+def err64(a, b):
+    return float(np.abs(a - b).max())
+
+
+def rel32(a, ref):
+    return float(np.abs(a - ref).max() / np.abs(ref).max())
+
+
+def graph(D, n, s, d, **kw):
+    return D.Graph(n, s, d, **kw)
+
+
+# --- structure ------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", ["rmat_small", "ragged", "tiny", "empty"])
+def test_structure_roundtrip(D, O, case):
+    say("structure", case)
+    if case == "rmat_small":
+        n, s, d = inputs.rmat_small()
+    elif case == "ragged":
+        n, s, d = inputs.erdos_renyi(1000, 7000, seed=2)
+        # duplicates and self pairs in the input are dropped
+        s = np.concatenate([s, s[:50], np.arange(10, dtype=np.int32)])
+        d = np.concatenate([d, d[:50], np.arange(10, dtype=np.int32)])
+    elif case == "tiny":
+        n, s, d = 3, np.array([0, 1], np.int32), np.array([1, 2], np.int32)
+    else:
+        n, s, d = 5, np.empty(0, np.int32), np.empty(0, np.int32)
+    ref = O.edge_set(n, s, d)
+    with graph(D, n, s, d) as g:
+        assert g.size() == (n, ref.size)
+        for direction in (D.DFPR_OUT, D.DFPR_IN):
+            gs, gd = g.edges(direction)
+            assert np.array_equal(edge_keys(n, gs, gd), ref)
+
+
+def test_apply_set_semantics(D, O):
+    say("apply set semantics")
+    n = 5
+    s = np.array([0, 0, 1, 2], np.int32)
+    d = np.array([1, 2, 2, 3], np.int32)
+    ds, dd = np.array([0, 3, 2, 0], np.int32), np.array([1, 4, 2, 2], np.int32)
+    is_, id_ = np.array([4, 4, 1, 3, 0], np.int32), np.array([0, 0, 2, 3, 2], np.int32)
+    ns, nd, dt, it = O.apply_batch(n, s, d, ds, dd, is_, id_)
+    with graph(D, n, s, d) as g:
+        ad, ai = g.apply_batch(ds, dd, is_, id_)
+        assert (ad, ai) == (dt.size, it.size)
+        for direction in (D.DFPR_OUT, D.DFPR_IN):
+            assert np.array_equal(edge_keys(n, *g.edges(direction)),
+                                  edge_keys(n, ns, nd))
+
+
+@pytest.mark.parametrize("frac", [1e-3, 5e-2, 0.3])
+def test_apply_batches_match_oracle(D, O, frac):
+    say("apply batches", frac)
+    n, s, d = inputs.rmat_small()
+    bs = inputs.batches(n, s, d, 3, seed=31, frac=frac)
+    cs, cd = s, d
+    with graph(D, n, s, d) as g:
+        for b in bs:
+            cs, cd, dt, it = O.apply_batch(n, cs, cd, b.del_src, b.del_dst,
+                                           b.ins_src, b.ins_dst)
+            ad, ai = g.apply(b)
+            assert (ad, ai) == (dt.size, it.size)
+        for direction in (D.DFPR_OUT, D.DFPR_IN):
+            assert np.array_equal(edge_keys(n, *g.edges(direction)),
+                                  edge_keys(n, cs, cd))
+
+
+def test_apply_row_relocation_and_growth(D, O):
+    say("relocation")
+    # a hub gains thousands of out- and in-edges: rows outgrow their slack
+    # and the spare tail of the adjacency arrays has to grow
+    n = 70000
+    s = np.arange(1, 200, dtype=np.int32)
+    d = np.zeros(199, np.int32)
+    ins_s = np.concatenate([np.zeros(69000, np.int32), np.arange(1000, 69999, dtype=np.int32)])
+    ins_d = np.concatenate([np.arange(1, 69001, dtype=np.int32), np.full(68999, 5, np.int32)])
+    ns, nd, dt, it = O.apply_batch(n, s, d, [], [], ins_s, ins_d)
+    with graph(D, n, s, d) as g:
+        ad, ai = g.apply_batch(np.empty(0, np.int32), np.empty(0, np.int32), ins_s, ins_d)
+        assert (ad, ai) == (0, it.size)
+        for direction in (D.DFPR_OUT, D.DFPR_IN):
+            assert np.array_equal(edge_keys(n, *g.edges(direction)),
+                                  edge_keys(n, ns, nd))
+
+
+def test_invalid_batch_is_rejected_whole(D, O):
+    say("invalid batch")
+    n, s, d = inputs.rmat(8, 1000, seed=3)
+    with graph(D, n, s, d) as g:
+        before = edge_keys(n, *g.edges())
+        with pytest.raises(D.DfprError) as ei:
+            g.apply_batch(np.array([0], np.int32), np.array([1], np.int32),
+                          np.array([2, n], np.int32), np.array([3, 4], np.int32))
+        assert ei.value.status == D.DFPR_EINVAL
+        assert np.array_equal(edge_keys(n, *g.edges()), before)
+
+
+# --- marking (Section 4.1.2, with self-loops) --------------------------------------
+
+def test_marking_frontier_example(D, O):
+    say("marking example")
+    with open(os.path.join(GOLD, "frontier_example.json")) as f:
+        ex = json.load(f)
+    n = ex["n"]
+    s, d = (np.array(x, np.int32) for x in zip(*ex["edges_before"]))
+    with graph(D, n, s, d) as g:
+        g.apply_batch(np.array([10], np.int32), np.array([11], np.int32),
+                      np.array([7], np.int32), np.array([9], np.int32))
+        aff, cnt = g.marks()
+        # the narrative's {8, 9, 11} plus the sources 7 and 10 (self-loops)
+        assert sorted(np.flatnonzero(aff).tolist()) == [7, 8, 9, 10, 11]
+        assert cnt == 5
+
+
+def test_marking_matches_oracle_rmat(D, O):
+    say("marking rmat")
+    n, s, d = inputs.rmat_small()
+    b = inputs.batches(n, s, d, 1, 1001, frac=1e-3)[0]
+    R, _, _ = O.pagerank(n, s, d)
+    ns, nd, dt, it = O.apply_batch(n, s, d, b.del_src, b.del_dst, b.ins_src, b.ins_dst)
+    src = np.concatenate([dt // n, it // n]).astype(np.int32)
+    ref = O.df_bb(n, (s, d), (ns, nd), src, R, max_iters=0)
+    with graph(D, n, s, d) as g:
+        g.apply(b)
+        aff, cnt = g.marks()
+        assert np.array_equal(aff, ref.affected)
+        assert cnt == ref.initial_marked
+
+
+# --- ranks --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_static_matches_oracle(D, O, prec):
+    say("static", prec)
+    n, s, d = inputs.rmat_small()
+    ref, _, _ = O.pagerank(n, s, d)
+    with graph(D, n, s, d, precision=prec, renormalize=int(prec == 32)) as g:
+        rc, st = g.static()
+        assert rc == D.DFPR_OK and st.converged
+        R = g.ranks()
+    if prec == 64:
+        assert err64(R, ref) < FP64_TOL
+        assert abs(R.sum() - 1) < 1e-8
+    else:
+        assert rel32(R, ref) < FP32_REL
+
+
+@pytest.mark.parametrize("mode", ["sync", "async"])
+@pytest.mark.parametrize("frac", [1e-3, 1e-2])
+def test_df_fp64_matches_oracle(D, O, mode, frac):
+    say("df fp64", mode, frac)
+    n, s, d = inputs.rmat_small()
+    R0, _, _ = O.pagerank(n, s, d)
+    b = inputs.batches(n, s, d, 1, 1001, frac=frac)[0]
+    ns, nd, res, ndel, nins = O.update(n, s, d, b, R0)
+    ref, _, _ = O.pagerank(n, ns, nd)
+    m = D.DFPR_SYNC if mode == "sync" else D.DFPR_ASYNC
+    with graph(D, n, s, d, mode=m) as g:
+        g.set_ranks(R0)                        # parity mode: R^{t-1} exact
+        assert g.apply(b) == (ndel, nins)
+        rc, st = g.update()
+        assert rc == D.DFPR_OK and st.converged, st.as_dict()
+        R = g.ranks()
+    say("  err", err64(R, ref), "sweeps", st.sweeps, "affected", st.affected,
+        "oracle iters", res.iters, "affected", int(res.affected.sum()))
+    assert err64(R, ref) < FP64_TOL
+    assert st.initial_marked == res.initial_marked
+    if mode == "sync":
+        # same algorithm as the oracle's Algorithm 1: same iteration count and
+        # affected set up to the rounding of borderline frontier decisions
+        assert abs(st.sweeps - res.iters) <= 1
+        assert abs(st.affected - int(res.affected.sum())) <= max(3, res.affected.sum() // 1000)
+
+
+@pytest.mark.parametrize("mode", ["sync", "async"])
+def test_df_fp32_matches_oracle(D, O, mode):
+    say("df fp32", mode)
+    n, s, d = inputs.rmat_small()
+    R0, _, _ = O.pagerank(n, s, d)
+    b = inputs.batches(n, s, d, 1, 1001, frac=1e-3)[0]
+    ns, nd, res, _, _ = O.update(n, s, d, b, R0)
+    ref, _, _ = O.pagerank(n, ns, nd)
+    m = D.DFPR_SYNC if mode == "sync" else D.DFPR_ASYNC
+    with graph(D, n, s, d, mode=m, precision=32, renormalize=1) as g:
+        g.set_ranks(R0)
+        g.apply(b)
+        rc, st = g.update()
+        assert rc >= 0
+        R = g.ranks()
+    say("  rel", rel32(R, ref), "abs", err64(R, ref), "sweeps", st.sweeps)
+    assert rel32(R, ref) < FP32_REL
+
+
+@pytest.mark.parametrize("mode", ["sync", "async"])
+@pytest.mark.parametrize("k", [7, 1000, 5000])
+def test_df_star_closed_form(D, O, mode, k):
+    say("star", mode, k)
+    # out-star -> bidirectional star; the closed forms fix both ends
+    a = 0.85
+    n = k + 1
+    s = np.zeros(k, np.int32)
+    d = np.arange(1, n, dtype=np.int32)
+    R0 = np.array([(1 - a) / (k + 1 - a)] + [1 / (k + 1 - a)] * k)
+    den = (2 - a) + k * (2 + a)
+    ref = np.array([((2 - a) + a * k) / den] + [2 / den] * k)
+    m = D.DFPR_SYNC if mode == "sync" else D.DFPR_ASYNC
+    with graph(D, n, s, d, mode=m) as g:
+        g.set_ranks(R0)
+        ad, ai = g.apply_batch(np.empty(0, np.int32), np.empty(0, np.int32),
+                               np.arange(1, n, dtype=np.int32), np.zeros(k, np.int32))
+        assert ai == k
+        rc, st = g.update()
+        assert rc == D.DFPR_OK
+        R = g.ranks()
+    assert err64(R, ref) < FP64_TOL
+
+
+@pytest.mark.parametrize("mode", ["sync", "async"])
+def test_df_empty_and_noop_batches_keep_ranks(D, O, mode):
+    say("empty batch", mode)
+    n, s, d = inputs.rmat(10, 8 << 10, seed=4)
+    m = D.DFPR_SYNC if mode == "sync" else D.DFPR_ASYNC
+    with graph(D, n, s, d, mode=m) as g:
+        g.static()
+        R = g.ranks()
+        rc, st = g.update()                     # nothing applied
+        assert rc == D.DFPR_OK and st.sweeps == 0
+        assert np.array_equal(g.ranks(), R)     # bit-identical
+        ad, ai = g.apply_batch(np.array([0], np.int32), np.array([0], np.int32),
+                               s[:1], d[:1])    # self pair + existing edge
+        assert (ad, ai) == (0, 0)
+        assert g.marks()[1] == 0
+        rc, st = g.update()
+        assert st.sweeps == 0 and np.array_equal(g.ranks(), R)
+
+
+@pytest.mark.parametrize("mode", ["sync", "async"])
+def test_df_sequential_batches_and_stability(D, O, mode):
+    say("sequential", mode)
+    n, s, d = inputs.rmat_small(seed=5)
+    bs = inputs.batches(n, s, d, 3, seed=55, frac=2e-3)
+    m = D.DFPR_SYNC if mode == "sync" else D.DFPR_ASYNC
+    cs, cd = s, d
+    with graph(D, n, s, d, mode=m) as g:
+        g.static()
+        R_start = g.ranks()
+        for b in bs:
+            g.apply(b)
+            rc, st = g.update()
+            assert rc == D.DFPR_OK
+            cs, cd, _, _ = O.apply_batch(n, cs, cd, b.del_src, b.del_dst, b.ins_src, b.ins_dst)
+            ref, _, _ = O.pagerank(n, cs, cd)
+            assert err64(g.ranks(), ref) < FP64_TOL
+        # stability round trip (Section 5.2.3): undo every batch in reverse
+        for b in reversed(bs):
+            g.apply_batch(b.ins_src, b.ins_dst, b.del_src, b.del_dst)
+            g.update()
+        assert np.array_equal(edge_keys(n, *g.edges()), edge_keys(n, s, d))
+        ref0, _, _ = O.pagerank(n, s, d)
+        assert err64(g.ranks(), ref0) < FP64_TOL
+        assert err64(g.ranks(), R_start) < 2 * FP64_TOL
+
+
+def test_df_ragged_small_graphs(D, O):
+    say("ragged small")
+    for seed, (n, m) in enumerate([(1, 0), (2, 1), (63, 200), (65, 300), (129, 2000)]):
+        if m:
+            _, s, d = inputs.erdos_renyi(n, m, seed=seed)
+        else:
+            s = d = np.empty(0, np.int32)
+        for mode in (D.DFPR_SYNC, D.DFPR_ASYNC):
+            with graph(D, n, s, d, mode=mode) as g:
+                g.static()
+                ref, _, _ = O.pagerank(n, s, d)
+                assert err64(g.ranks(), ref) < FP64_TOL
+                if n >= 2:
+                    b = inputs.Batch(s[:1].copy(), d[:1].copy(),
+                                     np.array([n - 1], np.int32), np.array([0], np.int32))
+                    ns, nd, _, _ = O.apply_batch(n, s, d, b.del_src, b.del_dst,
+                                                 b.ins_src, b.ins_dst)
+                    g.apply(b)
+                    rc, st = g.update()
+                    assert rc == D.DFPR_OK
+                    ref, _, _ = O.pagerank(n, ns, nd)
+                    assert err64(g.ranks(), ref) < FP64_TOL
+
+
+def test_naive_dynamic_matches_oracle(D, O):
+    say("naive dynamic")
+    n, s, d = inputs.rmat_small()
+    b = inputs.batches(n, s, d, 1, 7, frac=1e-2)[0]
+    ns, nd, _, _ = O.apply_batch(n, s, d, b.del_src, b.del_dst, b.ins_src, b.ins_dst)
+    ref, _, _ = O.pagerank(n, ns, nd)
+    with graph(D, n, s, d) as g:
+        g.static()
+        g.apply(b)
+        rc, st = g.naive_dynamic()
+        assert rc == D.DFPR_OK
+        assert err64(g.ranks(), ref) < FP64_TOL
