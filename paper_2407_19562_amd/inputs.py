@@ -298,3 +298,30 @@ def resident_mix(count: int, seed: int, n_lo: int = 1 << 16,
         m = int(round(n * degs[g]))
         scale = math.ceil(math.log2(n))
         yield rmat(scale, m, seed + 1 + g, n=n)
+
+
+# --- on-disk cache of generated inputs (same process tree / same box) ---------
+
+def cached(name: str, fn, *args, **kw):
+    """Returns fn(*args, **kw), memoised as an .npz under $DFPR_CACHE_DIR
+    (default: $TMPDIR/dfpr_inputs) so that several runs on one machine draw
+    the large graphs once.  The key is the name and the arguments."""
+    import hashlib
+    import os
+    import tempfile
+    root = os.environ.get("DFPR_CACHE_DIR",
+                          os.path.join(tempfile.gettempdir(), "dfpr_inputs"))
+    key = hashlib.sha1(repr((name, args, sorted(kw.items()))).encode()).hexdigest()[:16]
+    path = os.path.join(root, f"{name}_{key}.npz")
+    if os.path.exists(path):
+        with np.load(path, allow_pickle=False) as z:
+            return int(z["n"]), z["src"], z["dst"]
+    n, src, dst = fn(*args, **kw)
+    try:
+        os.makedirs(root, exist_ok=True)
+        tmp = path + f".{os.getpid()}.tmp.npz"
+        np.savez(tmp, n=np.int64(n), src=src, dst=dst)
+        os.replace(tmp, path)
+    except OSError:
+        pass
+    return n, src, dst
