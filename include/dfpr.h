@@ -59,8 +59,10 @@ extern "C" {
 
 /* scheduling of the rank iteration */
 #define DFPR_ASYNC 0 /* one persistent launch; in-place (Gauss-Seidel-like)
-                        ranks, per-vertex converged flags, no grid barrier
-                        (the lock-free variant, Algorithm 2)             */
+                        ranks, dynamic grabs of 256-vertex groups, no grid
+                        barrier; ends after a full sweep in which no rank
+                        moved by more than frontier_tol (the lock-free
+                        variant, Algorithm 2)                            */
 #define DFPR_SYNC 1  /* one launch per iteration; two rank vectors and an
                         L-infinity norm per iteration (the barrier-based
                         variant, Algorithm 1)                             */
@@ -82,11 +84,11 @@ typedef struct {
   int32_t kahan_min_degree; /* fp32: compensated sums for in-degree >= this */
   int32_t wave_min_degree;  /* in-degree at or above which a whole wavefront
                                gathers one vertex (else one lane each)      */
-  int32_t chunk;         /* worklist positions per dynamic grab (mult. of 64)*/
-  int32_t block_size;    /* threads per workgroup (multiple of 64, <= 1024) */
-  int32_t dense_div;     /* a sweep walks the whole vertex range instead of
-                            the worklist once affected > n / dense_div
-                            (0: never)                                      */
+  int32_t chunk;         /* vertices per dynamic grab: worklist positions in
+                            the synchronous scheme (multiple of 64), whole
+                            256-vertex groups (chunk / 256, at least one)
+                            in the lock-free scheme                         */
+  int32_t block_size;    /* threads per workgroup (64, 128, 192 or 256)     */
   int32_t renormalize;   /* fp32: rescale ranks to sum 1 (fp64 sum) after
                             each update                                     */
   int32_t timeout_ms;    /* watchdog for the persistent kernel (0: none)    */

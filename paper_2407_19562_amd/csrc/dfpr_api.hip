@@ -63,7 +63,6 @@ int check_params(const dfpr_params *p) {
     return fail(DFPR_EINVAL, "chunk must be a multiple of 64 in [64, 4096]");
   if (p->block_size < 64 || p->block_size > 256 || p->block_size % 64)
     return fail(DFPR_EINVAL, "block_size must be 64, 128, 192 or 256");
-  if (p->dense_div < 0) return fail(DFPR_EINVAL, "dense_div must be >= 0");
   if (p->timeout_ms < 0) return fail(DFPR_EINVAL, "timeout_ms must be >= 0");
   if (p->grid_blocks < 0 || (int64_t)p->grid_blocks * (p->block_size / 64) > 32768)
     return fail(DFPR_EINVAL, "grid_blocks * waves per block must be <= 32768");
@@ -77,7 +76,7 @@ static void release(dfpr_graph *g) {
                   g->in.off,  g->in.deg,  g->in.cap,  g->in.adj,
                   g->R[0],    g->R[1],    g->C[0],    g->C[1],
                   g->flags,   g->wl,      g->ctl,     g->sync_max,
-                  g->sync_grab, g->sync_len};
+                  g->sync_grab, g->sync_len, g->gflags, g->gwl};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (auto &s : g->scratch)
@@ -105,6 +104,12 @@ static int alloc_graph(dfpr_graph *g) {
   DFPR_HIP(hipMemsetAsync(g->flags, 0, fbytes, g->stream));
   DFPR_HIP(hipMalloc(&g->wl, n * 4));
   DFPR_HIP(hipMemsetAsync(g->wl, 0xFF, n * 4, g->stream));
+  g->ngroups = (int32_t)((n + kGroup - 1) / kGroup);
+  const size_t gbytes = ((size_t)g->ngroups + 3) / 4 * 4;
+  DFPR_HIP(hipMalloc(&g->gflags, gbytes));
+  DFPR_HIP(hipMemsetAsync(g->gflags, 0, gbytes, g->stream));
+  DFPR_HIP(hipMalloc(&g->gwl, (size_t)g->ngroups * 4));
+  DFPR_HIP(hipMemsetAsync(g->gwl, 0xFF, (size_t)g->ngroups * 4, g->stream));
   DFPR_HIP(hipMalloc(&g->ctl, sizeof(Ctl)));
   DFPR_HIP(hipMemsetAsync(g->ctl, 0, sizeof(Ctl), g->stream));
   DFPR_HIP(hipHostMalloc(&g->h_ctl, sizeof(Ctl), hipHostMallocDefault));
@@ -155,7 +160,6 @@ int dfpr_params_default(dfpr_params *p) {
   p->wave_min_degree = 32;
   p->chunk = 256;
   p->block_size = 256;
-  p->dense_div = 4;
   p->renormalize = 0;
   p->timeout_ms = 60000;
   p->grid_blocks = 0;

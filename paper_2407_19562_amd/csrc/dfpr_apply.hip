@@ -265,12 +265,19 @@ template <typename T>
 __global__ void k_mark_sources(int64_t S, const int64_t *segstart,
                                const unsigned long long *uk,
                                const uint8_t *status, AdjView out,
-                               const T *R, T *C, uint32_t *flags, int32_t *wl,
+                               const T *R, T *C, uint32_t *flags,
+                               uint32_t *gflags, int32_t *wl, int32_t *gwl,
                                Ctl *ctl) {
   const int lane = lane_id();
   const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  long long nc = 0, appended = 0;
+  long long appended = 0;
+  auto mark = [&](bool act, int32_t v) {
+    MarkOut o{false, false, -1};
+    if (act) o = mark_affected(flags, gflags, v);
+    appended += wave_append(o.vnew, v, wl, &ctl->tail, true);
+    wave_append(o.gnew, o.g, gwl, &ctl->gtail, true);
+  };
   for (int64_t s = wave; s < S; s += nwaves) {
     const int64_t a = segstart[s], b = segstart[s + 1];
     bool any = false;
@@ -284,35 +291,18 @@ __global__ void k_mark_sources(int64_t S, const int64_t *segstart,
     // u itself (implicit self-loop), then its current out-row
     for (int32_t t = -1; t < deg; t += kWave) {
       const int32_t idx = t + lane;
-      bool want = false;
-      int32_t v = -1;
-      if (idx < deg) {
-        v = idx < 0 ? u : out.adj[off + idx];
-        const uint32_t old = flag_set(flags, v, kVA | kRC);
-        want = !(old & kVA);
-        nc += !(old & kRC);
-      }
-      appended += wave_append(want, v, wl, &ctl->tail, false);
+      const bool act = idx < deg;
+      mark(act, act ? (idx < 0 ? u : out.adj[off + idx]) : -1);
     }
     // targets of the deleted edges of u (they were out-neighbours in G^{t-1})
     for (int64_t i = a; i < b; i += kWave) {
       const int64_t e = i + lane;
-      bool want = false;
-      int32_t v = -1;
-      if (e < b && !(uk[e] & 1ull) && (status[e] & kApplied)) {
-        v = (int32_t)((uk[e] >> 1) & 0x7FFFFFFFull);
-        const uint32_t old = flag_set(flags, v, kVA | kRC);
-        want = !(old & kVA);
-        nc += !(old & kRC);
-      }
-      appended += wave_append(want, v, wl, &ctl->tail, false);
+      const bool act = e < b && !(uk[e] & 1ull) && (status[e] & kApplied);
+      mark(act, act ? (int32_t)((uk[e] >> 1) & 0x7FFFFFFFull) : -1);
     }
   }
-  nc = wave_sum(nc);
-  if (lane == 0) {
-    if (nc) atomicAdd((unsigned long long *)&ctl->nc, (unsigned long long)nc);
-    if (appended) atomicAdd((unsigned long long *)&ctl->marked, (unsigned long long)appended);
-  }
+  if (lane == 0 && appended)
+    atomicAdd((unsigned long long *)&ctl->marked, (unsigned long long)appended);
 }
 
 }  // namespace
@@ -465,11 +455,11 @@ int apply_batch(dfpr_graph *g, int64_t nd, const int32_t *ds,
     if (g->elem == 8)
       k_mark_sources<double><<<blocks, 256, 0, s>>>(
           S[0], seg[0], uk[0], st[0], o, (const double *)g->R[g->cur],
-          (double *)g->C[g->cur], g->flags, g->wl, g->ctl);
+          (double *)g->C[g->cur], g->flags, g->gflags, g->wl, g->gwl, g->ctl);
     else
       k_mark_sources<float><<<blocks, 256, 0, s>>>(
           S[0], seg[0], uk[0], st[0], o, (const float *)g->R[g->cur],
-          (float *)g->C[g->cur], g->flags, g->wl, g->ctl);
+          (float *)g->C[g->cur], g->flags, g->gflags, g->wl, g->gwl, g->ctl);
     DFPR_HIP(hipGetLastError());
   }
   DFPR_HIP(hipMemcpyAsync(g->h_ctl, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));

@@ -11,8 +11,10 @@
 //   ranks R[2][n] and contributions C[2][n] = R / (out-degree + 1), fp64 or
 //   fp32; only R[cur], C[cur] are meaningful between calls (the second
 //   buffer is the Jacobi target of synchronous iterations)
-//   flags[n] bytes: bit 0 affected (V_A), bit 1 not converged (R_C)
+//   flags[n] bytes: bit 0 affected (V_A), bit 2 out-neighbours marked
 //   worklist wl[n] int32 (unused slots hold -1), appended through ctl->tail
+//   per 256-vertex group: gflags bytes (bit 0: listed) and the group
+//   worklist gwl that the lock-free scheme sweeps
 //   Ctl: counters and the scheduling word of the persistent kernel
 #pragma once
 
@@ -30,14 +32,19 @@ constexpr int kMaxIters = 8000;  // sweep index field holds 13 bits
 
 // Flag bits in the per-vertex byte.
 constexpr uint32_t kVA = 1u;  // affected
-constexpr uint32_t kRC = 2u;  // rank not yet converged
+constexpr uint32_t kEX = 4u;  // all out-neighbours marked (synchronous DF)
+
+// Vertices are also grouped by id into aligned groups of kGroup; the
+// lock-free scheme schedules whole groups.  Flag bit in the per-group byte:
+constexpr int kGroup = 256;
+constexpr int kGroupShift = 8;
+constexpr uint32_t kGA = 1u;  // group holds an affected vertex (listed)
 
 // Scheduling word of the persistent kernel (one 64-bit atomic):
-//   bit 63 done, bit 62 dense sweeps, bit 61 stopped at the sweep cap,
+//   bit 63 done, bit 61 stopped at the sweep cap,
 //   bits 48..60 sweep index, bits 16..47 cursor, bits 0..15 workers that
 //   hold a chunk.
 constexpr uint64_t kDone = 1ull << 63;
-constexpr uint64_t kDense = 1ull << 62;
 constexpr uint64_t kCapped = 1ull << 61;
 constexpr int kSweepShift = 48;
 constexpr uint64_t kSweepMask = 0x1FFFull;
@@ -45,13 +52,18 @@ constexpr int kCursorShift = 16;
 constexpr uint64_t kCursorMask = 0xFFFFFFFFull;
 constexpr uint64_t kInflightMask = 0xFFFFull;
 
-// Device control block of one graph.
+// Device control block of one graph.  The words every wavefront of the
+// persistent kernel touches sit on cache lines of their own.
 struct Ctl {
-  unsigned long long state;        // async scheduling word
-  unsigned long long tail;         // worklist length
-  long long nc;                    // vertices with R_C set
-  long long marked;                // vertices appended by the batch marking
-  unsigned long long vertices;     // stats of the running update
+  alignas(128) unsigned long long state;  // async scheduling word
+  alignas(128) unsigned long long tail;   // vertex worklist length
+  alignas(128) unsigned long long gtail;  // group worklist length
+  alignas(128) long long change_sweep;    // last sweep in which a claim saw a
+                                          // change above the frontier tol
+  alignas(128) int abort;                 // watchdog fired
+  alignas(128) long long marked;          // vertices affected by the marking
+  long long newly;                        // vertices affected during the update
+  unsigned long long vertices;            // stats of the running update
   unsigned long long edges;
   unsigned long long out_scanned;
   unsigned long long ins_applied;  // apply_batch results (out direction)
@@ -61,9 +73,9 @@ struct Ctl {
   unsigned long long adj_used[2];  // bump pointers: out, in
   int invalid;                     // an input id was out of range
   int overflow;                    // an adjacency array ran out of slots
-  int abort;                       // watchdog fired
   int sync_done;                   // synchronous iteration finished
   int sync_final;                  // iterations made by the synchronous loop
+  int sync_conv;                   // synchronous loop met the tolerance
   int pad;
   double sum;                      // fp64 rank sum (renormalisation)
 };
@@ -98,6 +110,9 @@ struct dfpr_graph {
   int elem = 8;  // bytes per rank (8 fp64, 4 fp32)
   uint32_t *flags = nullptr;
   int32_t *wl = nullptr;
+  int32_t ngroups = 0;
+  uint32_t *gflags = nullptr;  // [ngroups] bytes
+  int32_t *gwl = nullptr;      // group worklist [ngroups], unused slots -1
   dfpr::Ctl *ctl = nullptr;
   dfpr::Ctl *h_ctl = nullptr;           // pinned host mirror
   unsigned long long *sync_max = nullptr;   // [kMaxIters] bit patterns
@@ -230,6 +245,24 @@ __device__ __forceinline__ int wave_append(bool want, int32_t v,
       wl[pos] = v;
   }
   return cnt;
+}
+
+// Marks v affected and lists its group.  vnew / gnew report whether v / its
+// group were new.  Coherent (agent-scope) pre-checks skip the atomics when
+// the bits are already set.
+struct MarkOut {
+  bool vnew;
+  bool gnew;
+  int32_t g;
+};
+
+__device__ __forceinline__ MarkOut mark_affected(uint32_t *flags,
+                                                 uint32_t *gflags, int32_t v) {
+  MarkOut o{false, false, v >> kGroupShift};
+  if (!(flag_byte(flags, v, true) & kVA)) o.vnew = !(flag_set(flags, v, kVA) & kVA);
+  if (!(flag_byte(gflags, o.g, true) & kGA))
+    o.gnew = !(flag_set(gflags, o.g, kGA) & kGA);
+  return o;
 }
 
 }  // namespace dfpr

@@ -2,8 +2,9 @@
 // convergence (Section 4; Algorithms 1 and 2), plus static / naive-dynamic
 // PageRank (Algorithm 3; Section 3.5.1) and small helpers.
 //
-// Work unit: one wavefront takes a group of 64 worklist positions (or 64
-// consecutive vertex ids in a dense sweep), one vertex per lane.
+// Work unit: one wavefront takes 64 vertices, one per lane: 64 worklist
+// positions (synchronous scheme, static) or a quarter of a 256-vertex id
+// group (lock-free scheme).
 //   gather: a lane sums its own in-row when the in-degree is below
 //     wave_min_degree (16-byte index loads, two accumulators); rows at or
 //     above it are gathered by the whole wavefront, one row at a time,
@@ -32,6 +33,9 @@
 #include <cmath>
 #include <cstring>
 
+#include <rocprim/device/device_select.hpp>
+#include <rocprim/iterator/counting_iterator.hpp>
+
 #include "dfpr_common.h"
 
 namespace dfpr {
@@ -53,9 +57,11 @@ struct RankArgs {
   T *Cw;
   uint32_t *flags;
   int32_t *wl;
+  uint32_t *gflags;
+  int32_t *gwl;
   Ctl *ctl;
   double alpha, base, tol, ftol;
-  int32_t wave_min, kahan_min, chunk, dense_div, max_iters;
+  int32_t wave_min, kahan_min, chunk, max_iters;
   unsigned long long timeout_ticks;
   unsigned long long *sync_max;
   unsigned long long *sync_grab;
@@ -74,239 +80,241 @@ __device__ __forceinline__ T ldc(const T *C, int32_t u) {
     return C[u];
 }
 
-// --- per-lane gather over a light in-row -------------------------------------
+// One step of a wavefront covers kRows = 256 vertices, four per lane
+// (row r = k * 64 + lane holds the lane's k-th vertex).
+constexpr int kQ = 4;
+constexpr int kRows = kQ * kWave;
+// independent row entries (and then contributions) each lane loads per round
+constexpr int kUnroll = 4;
 
-template <bool COH>
-__device__ __forceinline__ double gather_lane(const double *C,
-                                              const int32_t *row, int32_t deg,
-                                              bool) {
-  double s0 = 0.0, s1 = 0.0;
-  int32_t k = 0;
-  for (; k + 4 <= deg; k += 4) {
-    const int4 q = *reinterpret_cast<const int4 *>(row + k);
-    const double a = ldc<double, COH>(C, q.x), b = ldc<double, COH>(C, q.y);
-    const double c = ldc<double, COH>(C, q.z), d = ldc<double, COH>(C, q.w);
-    s0 += a + b;
-    s1 += c + d;
-  }
-  for (; k < deg; ++k) s0 += ldc<double, COH>(C, row[k]);
-  return s0 + s1;
+// Per-wavefront LDS: the flattened edge list of the current step (prefix of
+// the row lengths and the row starts) and per-row accumulators.
+template <typename T>
+struct WaveLds {
+  int32_t pre[kRows + 1];
+  int64_t off[kRows];
+  double acc[kRows];  // fp64 sums (fp64 ranks; fp32 rows at/above the
+                      // compensation threshold)
+  float accf[sizeof(T) == 4 ? kRows : 1];  // fp32 sums (fp32 rows below it)
+};
+
+// Orders LDS traffic of the lanes of one wavefront (no cross-wave sync).
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// fp32: plain or compensated (Kahan) single-precision sums; returns the
-// compensated value widened to fp64.
-template <bool COH>
-__device__ __forceinline__ double gather_lane(const float *C,
-                                              const int32_t *row, int32_t deg,
-                                              bool kahan) {
-  if (!kahan) {
-    float s0 = 0.f, s1 = 0.f;
-    int32_t k = 0;
-    for (; k + 4 <= deg; k += 4) {
-      const int4 q = *reinterpret_cast<const int4 *>(row + k);
-      const float a = ldc<float, COH>(C, q.x), b = ldc<float, COH>(C, q.y);
-      const float c = ldc<float, COH>(C, q.z), d = ldc<float, COH>(C, q.w);
-      s0 += a + b;
-      s1 += c + d;
-    }
-    for (; k < deg; ++k) s0 += ldc<float, COH>(C, row[k]);
-    return (double)s0 + (double)s1;
-  }
-  float s = 0.f, comp = 0.f;
-  int32_t k = 0;
-  for (; k + 4 <= deg; k += 4) {
-    const int4 q = *reinterpret_cast<const int4 *>(row + k);
-    const float x[4] = {ldc<float, COH>(C, q.x), ldc<float, COH>(C, q.y),
-                        ldc<float, COH>(C, q.z), ldc<float, COH>(C, q.w)};
+__device__ __forceinline__ int32_t wave_incl_scan(int32_t x) {
+  const int lane = lane_id();
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const float y = x[j] - comp;
-      const float t = s + y;
-      comp = (t - s) - y;
-      s = t;
-    }
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int32_t y = __shfl_up(x, o);
+    if (lane >= o) x += y;
   }
-  for (; k < deg; ++k) {
-    const float y = ldc<float, COH>(C, row[k]) - comp;
-    const float t = s + y;
-    comp = (t - s) - y;
-    s = t;
-  }
-  return (double)s - (double)comp;
+  return x;
 }
 
-// --- whole-wavefront gather over a heavy in-row --------------------------------
+// Largest row r with pre[r] <= e (pre non-decreasing, pre[kRows] > e).
+__device__ __forceinline__ int find_owner(const int32_t *pre, int32_t e) {
+  int lo = 0, hi = kRows;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= e)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
 
+// Publishes the 256 rows (off, len) of the step as one flattened range in
+// LDS; returns its total length.  Clears the accumulators.
+template <typename T>
+__device__ __forceinline__ int32_t flatten_rows(WaveLds<T> &L, const int64_t *off,
+                                               const int32_t *len) {
+  const int lane = lane_id();
+  wave_lds_fence();
+  int32_t base = 0;
+#pragma unroll
+  for (int k = 0; k < kQ; ++k) {
+    const int32_t incl = wave_incl_scan(len[k]);
+    const int r = k * kWave + lane;
+    L.pre[r] = base + incl - len[k];
+    L.off[r] = off[k];
+    L.acc[r] = 0.0;
+    if constexpr (sizeof(T) == 4) L.accf[r] = 0.f;
+    base += __shfl(incl, kWave - 1);
+  }
+  if (lane == 0) L.pre[kRows] = base;
+  wave_lds_fence();
+  return base;
+}
+
+// Sums over the in-rows of the step's 256 vertices, edge-parallel: every
+// round loads kUnroll x 64 row entries, then as many contributions, all
+// independent, and adds them to the owners' LDS accumulators.
 template <typename T, bool COH>
-__device__ __forceinline__ double gather_wave(const T *C, const int32_t *row,
-                                              int32_t deg, bool kahan) {
+__device__ __forceinline__ void gather_flat(const RankArgs<T> &A, WaveLds<T> &L,
+                                            const int64_t *off,
+                                            const int32_t *deg, double *sum) {
   const int lane = lane_id();
-  if constexpr (sizeof(T) == 8) {
-    double s0 = 0.0, s1 = 0.0;
-    int32_t k = lane;
-    for (; k + 3 * kWave < deg; k += 4 * kWave) {
-      const int32_t i0 = row[k], i1 = row[k + kWave];
-      const int32_t i2 = row[k + 2 * kWave], i3 = row[k + 3 * kWave];
-      const double a = ldc<T, COH>(C, i0), b = ldc<T, COH>(C, i1);
-      const double c = ldc<T, COH>(C, i2), d = ldc<T, COH>(C, i3);
-      s0 += a + b;
-      s1 += c + d;
-    }
-    for (; k < deg; k += kWave) s0 += ldc<T, COH>(C, row[k]);
-    return wave_sum(s0 + s1);
-  } else {
-    float s = 0.f, comp = 0.f;
-    int32_t k = lane;
-    for (; k + 3 * kWave < deg; k += 4 * kWave) {
-      const int32_t i0 = row[k], i1 = row[k + kWave];
-      const int32_t i2 = row[k + 2 * kWave], i3 = row[k + 3 * kWave];
-      const float x[4] = {ldc<T, COH>(C, i0), ldc<T, COH>(C, i1),
-                          ldc<T, COH>(C, i2), ldc<T, COH>(C, i3)};
+  const int32_t total = flatten_rows(L, off, deg);
+  for (int32_t base = 0; base < total; base += kUnroll * kWave) {
+    int own[kUnroll];
+    int32_t idx[kUnroll];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (kahan) {
-          const float y = x[j] - comp;
-          const float t = s + y;
-          comp = (t - s) - y;
-          s = t;
-        } else {
-          s += x[j];
-        }
+    for (int j = 0; j < kUnroll; ++j) {
+      const int32_t e = base + j * kWave + lane;
+      own[j] = -1;
+      idx[j] = 0;
+      if (e < total) {
+        own[j] = find_owner(L.pre, e);
+        idx[j] = A.in_adj[L.off[own[j]] + (e - L.pre[own[j]])];
       }
     }
-    for (; k < deg; k += kWave) {
-      const float xv = ldc<T, COH>(C, row[k]);
-      if (kahan) {
-        const float y = xv - comp;
-        const float t = s + y;
-        comp = (t - s) - y;
-        s = t;
+    T c[kUnroll];
+#pragma unroll
+    for (int j = 0; j < kUnroll; ++j)
+      c[j] = own[j] >= 0 ? ldc<T, COH>(A.Cr, idx[j]) : (T)0;
+#pragma unroll
+    for (int j = 0; j < kUnroll; ++j) {
+      if (own[j] < 0) continue;
+      if constexpr (sizeof(T) == 8) {
+        atomicAdd(&L.acc[own[j]], (double)c[j]);
       } else {
-        s += xv;
+        const int32_t dlen = L.pre[own[j] + 1] - L.pre[own[j]];
+        if (dlen >= A.kahan_min)
+          atomicAdd(&L.acc[own[j]], (double)c[j]);
+        else
+          atomicAdd(&L.accf[own[j]], (float)c[j]);
       }
     }
-    return wave_sum((double)s - (double)comp);
+  }
+  wave_lds_fence();
+#pragma unroll
+  for (int k = 0; k < kQ; ++k) {
+    const int r = k * kWave + lane;
+    sum[k] = L.acc[r];
+    if constexpr (sizeof(T) == 4) sum[k] += (double)L.accf[r];
   }
 }
 
-// Marks w affected (and not converged in the lock-free scheme); returns true
-// when w was not affected before (the caller appends it).
-template <int MODE>
-__device__ __forceinline__ bool mark_vertex(uint32_t *flags, int32_t w,
-                                            long long &nc) {
-  if constexpr (MODE == kAsync) {
-    const uint32_t b = flag_byte(flags, w, true);
-    if ((b & (kVA | kRC)) == (kVA | kRC)) return false;
-    const uint32_t old = flag_set(flags, w, kVA | kRC);
-    nc += (old & kRC) ? 0 : 1;
-    return !(old & kVA);
-  } else {
-    const uint32_t b = flag_byte(flags, w, false);
-    if (b & kVA) return false;
-    const uint32_t old = flag_set(flags, w, kVA);
-    return !(old & kVA);
-  }
+// Synchronous scheme: marks w affected; true when w is newly affected.
+__device__ __forceinline__ bool mark_vertex_sync(uint32_t *flags, int32_t w) {
+  if (flag_byte(flags, w, false) & kVA) return false;
+  return !(flag_set(flags, w, kVA) & kVA);
 }
 
-// Processes one vertex per lane (v < 0: idle lane).  All 64 lanes call it.
+// Frontier expansion over the out-rows of the step's expanding vertices,
+// flattened like the gather.  Synchronous scheme: out-neighbours get the
+// affected flag (the worklist is rebuilt from the flags after the
+// iteration).  Lock-free scheme: newly affected out-neighbours also get
+// their group listed.
 template <typename T, int MODE>
-__device__ __forceinline__ void process_group(const RankArgs<T> &A, int32_t v,
-                                              Counters &cnt, double &maxdr,
-                                              long long &nc) {
-  constexpr bool COH = MODE == kAsync;
+__device__ __forceinline__ void expand_flat(const RankArgs<T> &A, WaveLds<T> &L,
+                                            const int64_t *oo,
+                                            const int32_t *od,
+                                            long long &newly) {
   const int lane = lane_id();
-  const bool valid = v >= 0;
-  int64_t off = 0;
-  int32_t deg = 0;
-  if (valid) {
-    off = A.in_off[v];
-    deg = A.in_deg[v];
+  const int32_t total = flatten_rows(L, oo, od);
+  for (int32_t base = 0; base < total; base += kUnroll * kWave) {
+    int32_t w[kUnroll];
+#pragma unroll
+    for (int j = 0; j < kUnroll; ++j) {
+      const int32_t e = base + j * kWave + lane;
+      w[j] = -1;
+      if (e < total) {
+        const int o = find_owner(L.pre, e);
+        w[j] = A.out_adj[L.off[o] + (e - L.pre[o])];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kUnroll; ++j) {
+      if constexpr (MODE == kAsync) {
+        MarkOut o{false, false, -1};
+        if (w[j] >= 0) o = mark_affected(A.flags, A.gflags, w[j]);
+        newly += o.vnew ? 1 : 0;
+        wave_append(o.gnew, o.g, A.gwl, &A.ctl->gtail, true);
+      } else {
+        if (w[j] >= 0) mark_vertex_sync(A.flags, w[j]);
+      }
+    }
   }
-  const bool heavy = valid && deg >= A.wave_min;
-  double sum = 0.0;
-  if (valid && !heavy)
-    sum = gather_lane<COH>(A.Cr, A.in_adj + off, deg, deg >= A.kahan_min);
-  uint64_t hm = __ballot(heavy);
-  while (hm) {
-    const int l = __ffsll((long long)hm) - 1;
-    hm &= hm - 1;
-    const int64_t o = __shfl(off, l);
-    const int32_t d = __shfl(deg, l);
-    const double part = gather_wave<T, COH>(A.Cr, A.in_adj + o, d, d >= A.kahan_min);
-    if (lane == l) sum = part;
-  }
+}
 
-  bool expand = false;
-  int32_t od = 0;
-  if (valid) {
-    const double selfc = (double)ldc<T, COH>(A.Cr, v);
-    const double r = A.base + A.alpha * (sum + selfc);
+// Processes one step: four vertices per lane (v[k] < 0: empty slot).  All
+// 64 lanes call it.  `moved` is set when a rank changed by more than the
+// frontier tolerance; `maxdr` tracks the largest change.
+template <typename T, int MODE>
+__device__ __forceinline__ void process_step(const RankArgs<T> &A, WaveLds<T> &L,
+                                             const int32_t *v, Counters &cnt,
+                                             double &maxdr, long long &newly,
+                                             bool &moved) {
+  constexpr bool COH = MODE == kAsync;
+  int64_t off[kQ];
+  int32_t deg[kQ];
+#pragma unroll
+  for (int k = 0; k < kQ; ++k) {
+    off[k] = 0;
+    deg[k] = 0;
+    if (v[k] >= 0) {
+      off[k] = A.in_off[v[k]];
+      deg[k] = A.in_deg[v[k]];
+    }
+  }
+  double sum[kQ];
+  gather_flat<T, COH>(A, L, off, deg, sum);
+
+  bool expand[kQ];
+  int32_t od[kQ];
+  int64_t oo[kQ];
+  bool any_expand = false;
+#pragma unroll
+  for (int k = 0; k < kQ; ++k) {
+    expand[k] = false;
+    od[k] = 0;
+    oo[k] = 0;
+    if (v[k] < 0) continue;
+    const int32_t x = v[k];
+    const double selfc = (double)ldc<T, COH>(A.Cr, x);
+    const double r = A.base + A.alpha * (sum[k] + selfc);
     const T rT = (T)r;
-    const T old = COH ? load_agent(A.Rr + v) : A.Rr[v];
+    const T old = COH ? load_agent(A.Rr + x) : A.Rr[x];
     const double dr = fabs((double)rT - (double)old);
-    od = A.out_deg[v];
-    const T cT = (T)(r / (double)(od + 1));
+    const int32_t d = A.out_deg[x];
+    const T cT = (T)(r / (double)(d + 1));
     if constexpr (COH) {
-      store_agent(A.Rw + v, rT);
-      store_agent(A.Cw + v, cT);
+      store_agent(A.Rw + x, rT);
+      store_agent(A.Cw + x, cT);
     } else {
-      A.Rw[v] = rT;
-      A.Cw[v] = cT;
+      A.Rw[x] = rT;
+      A.Cw[x] = cT;
     }
     cnt.vertices += 1;
-    cnt.edges += (unsigned long long)deg + 1;
-    if constexpr (MODE != kAll) expand = dr > A.ftol;
-    if constexpr (MODE == kAsync) {
-      // own R_C: set while dr > tol (the self-loop re-marks it when the
-      // change exceeds the frontier tolerance; the tol test clears it)
-      const uint32_t b = flag_byte(A.flags, v, true);
-      if (dr > A.tol) {
-        if (!(b & kRC)) {
-          const uint32_t o2 = flag_set(A.flags, v, kRC);
-          nc += (o2 & kRC) ? 0 : 1;
+    cnt.edges += (unsigned long long)deg[k] + 1;
+    maxdr = dr > maxdr ? dr : maxdr;
+    if constexpr (MODE != kAll) {
+      if (dr > A.ftol) {
+        moved = true;
+        // a vertex that already marked all its out-neighbours has nothing
+        // left to mark: affected flags are never cleared within an update
+        if (!(flag_byte(A.flags, x, COH) & kEX)) {
+          expand[k] = true;
+          od[k] = d;
+          oo[k] = A.out_off[x];
+          cnt.out_scanned += (unsigned long long)d;
+          any_expand = any_expand || d > 0;
         }
-      } else if (b & kRC) {
-        const uint32_t o2 = flag_clear(A.flags, v, kRC);
-        nc -= (o2 & kRC) ? 1 : 0;
       }
-    } else {
-      maxdr = dr > maxdr ? dr : maxdr;
     }
   }
   if constexpr (MODE == kAll) return;
-
-  // frontier expansion over out-rows (the self-loop is handled above)
-  int64_t oo = 0;
-  if (expand) oo = A.out_off[v];
-  const bool oheavy = expand && od >= A.wave_min;
-  const int32_t my = (expand && !oheavy) ? od : 0;
-  if (expand) cnt.out_scanned += (unsigned long long)od;
-  const int32_t trips = wave_max(my);
-  for (int32_t k = 0; k < trips; ++k) {
-    bool want = false;
-    int32_t w = -1;
-    if (k < my) {
-      w = A.out_adj[oo + k];
-      want = mark_vertex<MODE>(A.flags, w, nc);
-    }
-    wave_append(want, w, A.wl, &A.ctl->tail, COH);
-  }
-  uint64_t om = __ballot(oheavy);
-  while (om) {
-    const int l = __ffsll((long long)om) - 1;
-    om &= om - 1;
-    const int64_t o = __shfl(oo, l);
-    const int32_t d = __shfl(od, l);
-    for (int32_t t = 0; t < d; t += kWave) {
-      bool want = false;
-      int32_t w = -1;
-      if (t + lane < d) {
-        w = A.out_adj[o + t + lane];
-        want = mark_vertex<MODE>(A.flags, w, nc);
-      }
-      wave_append(want, w, A.wl, &A.ctl->tail, COH);
-    }
-  }
+  if (__ballot(any_expand) != 0) expand_flat<T, MODE>(A, L, oo, od, newly);
+#pragma unroll
+  for (int k = 0; k < kQ; ++k)
+    if (expand[k]) flag_set(A.flags, v[k], kEX);
 }
 
 template <typename T>
@@ -321,33 +329,38 @@ __device__ __forceinline__ void flush_counters(Ctl *ctl, Counters &c) {
   }
 }
 
-// Sweep-end decision, lane 0 only.
+// Sweep-end decision, lane 0 only, on a state word W read with a relaxed
+// load whose cursor reached the end of the group worklist.
+//
+// Convergence: every claim that saw a rank change above the frontier
+// tolerance raises change_sweep to the sweep index current when it
+// finishes (a returning atomic, performed before the claim drops its
+// in-flight mark).  Sweep S may end the launch only when no claim is held
+// and change_sweep < S: then every group was recomputed in S from ranks
+// that no later change above the frontier tolerance has touched, and no
+// vertex moved by more than that in S.  In Algorithm 2's terms every R_C
+// is 0 and no change is left to propagate.  Otherwise the next sweep
+// starts at once, without waiting for claims still held (no barrier).
 template <typename T>
-__device__ void sweep_end(const RankArgs<T> &A) {
+__device__ void sweep_end(const RankArgs<T> &A, unsigned long long W) {
   unsigned long long *st = &A.ctl->state;
-  const unsigned long long W =
-      __hip_atomic_load(st, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-  if (W & kDone) return;
-  const bool dense = W & kDense;
-  const unsigned long long tail = load_agent(&A.ctl->tail);
-  const unsigned long long bound = dense ? (unsigned long long)A.n : tail;
+  const unsigned long long bound = load_agent(&A.ctl->gtail);
   const unsigned long long cur = (W >> kCursorShift) & kCursorMask;
   if (cur < bound) return;
   const unsigned long long sweep = (W >> kSweepShift) & kSweepMask;
   const unsigned long long inflight = W & kInflightMask;
-  const long long nc = load_agent(&A.ctl->nc);
+  const long long cs = load_agent(&A.ctl->change_sweep);
   unsigned long long nw;
-  if (nc > 0) {
+  if (cs >= (long long)sweep) {
     const unsigned long long ns = sweep + 1;
-    if ((long long)ns >= A.max_iters) {
+    if ((long long)ns >= A.max_iters)
       nw = kDone | kCapped | (ns << kSweepShift);
-    } else {
-      const bool d = dense || (A.dense_div > 0 &&
-                               tail * (unsigned long long)A.dense_div >
-                                   (unsigned long long)A.n);
-      nw = (d ? kDense : 0ull) | (ns << kSweepShift) | inflight;
-    }
+    else
+      nw = (ns << kSweepShift) | inflight;
   } else if (inflight == 0) {
+    // confirm once with acquire ordering before ending the launch
+    if (__hip_atomic_load(st, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != W) return;
+    if (load_agent(&A.ctl->change_sweep) >= (long long)sweep) return;
     nw = kDone | ((sweep + 1) << kSweepShift);
   } else {
     return;
@@ -358,32 +371,40 @@ __device__ void sweep_end(const RankArgs<T> &A) {
                                        __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The lock-free persistent kernel.  A claim takes `chunk / 256` positions of
+// the group worklist (at least one); each affected vertex of a claimed group
+// is recomputed in place.
 template <typename T>
 __global__ void __launch_bounds__(256) k_df_async(RankArgs<T> A) {
+  __shared__ WaveLds<T> lds[256 / kWave];
+  WaveLds<T> &L = lds[threadIdx.x / kWave];
   const int lane = lane_id();
   Counters cnt;
   const unsigned long long t_start = wall_clock64();
-  const unsigned long long chunk = (unsigned long long)A.chunk;
-  const unsigned long long grab = (chunk << kCursorShift) | 1ull;
+  // groups per claim; at least one so the cursor always advances
+  const unsigned long long per =
+      A.chunk >= kGroup ? (unsigned long long)(A.chunk / kGroup) : 1ull;
+  const unsigned long long grab = (per << kCursorShift) | 1ull;
   unsigned polls = 0;
   double unused = 0.0;
+  long long newly = 0;
   while (true) {
-    unsigned long long W = 0, tl = 0;
+    unsigned long long W = 0;
     int ab = 0;
     if (lane == 0) {
       W = load_agent(&A.ctl->state);
-      tl = load_agent(&A.ctl->tail);
-      ab = load_agent(&A.ctl->abort);
+      if ((++polls & 15u) == 0) ab = load_agent(&A.ctl->abort);
     }
     W = bcast0(W);
-    tl = bcast0(tl);
     ab = __builtin_amdgcn_readfirstlane(ab);
     if ((W & kDone) || ab) break;
-    const unsigned long long bound = (W & kDense) ? (unsigned long long)A.n : tl;
-    if (((W >> kCursorShift) & kCursorMask) >= bound) {
-      if (lane == 0) sweep_end(A);
-      __builtin_amdgcn_s_sleep(2);
-      if (A.timeout_ticks && ((++polls & 63u) == 0)) {
+    unsigned long long gt = 0;
+    if (lane == 0) gt = load_agent(&A.ctl->gtail);
+    gt = bcast0(gt);
+    if (((W >> kCursorShift) & kCursorMask) >= gt) {
+      if (lane == 0) sweep_end(A, W);
+      __builtin_amdgcn_s_sleep(32);
+      if (A.timeout_ticks && ((polls & 63u) == 0)) {
         const bool late = wall_clock64() - t_start > A.timeout_ticks;
         if (late) {
           if (lane == 0) store_agent(&A.ctl->abort, 1);
@@ -396,54 +417,63 @@ __global__ void __launch_bounds__(256) k_df_async(RankArgs<T> A) {
     if (lane == 0) {
       W2 = __hip_atomic_fetch_add(&A.ctl->state, grab, __ATOMIC_RELAXED,
                                   __HIP_MEMORY_SCOPE_AGENT);
-      tl = load_agent(&A.ctl->tail);
+      gt = load_agent(&A.ctl->gtail);
     }
     W2 = bcast0(W2);
-    tl = bcast0(tl);
+    gt = bcast0(gt);
     if (W2 & kDone) break;
-    const bool dn = W2 & kDense;
     const unsigned long long p = (W2 >> kCursorShift) & kCursorMask;
-    const unsigned long long bnd = dn ? (unsigned long long)A.n : tl;
-    if (p >= bnd) {
+    if (p >= gt) {
       if (lane == 0)
         __hip_atomic_fetch_sub(&A.ctl->state, 1ull, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
       continue;
     }
-    const unsigned long long end = p + chunk < bnd ? p + chunk : bnd;
-    long long nc = 0;
-    for (unsigned long long g0 = p; g0 < end; g0 += kWave) {
-      const unsigned long long pos = g0 + lane;
-      int32_t v = -1;
-      if (pos < end) {
-        if (dn) {
-          v = (int32_t)pos;
-          if (!(flag_byte(A.flags, v, true) & kVA)) v = -1;
-        } else {
-          v = load_agent(A.wl + pos);
-        }
+    const unsigned long long end = p + per < gt ? p + per : gt;
+    bool moved = false;
+    for (unsigned long long gp = p; gp < end; ++gp) {
+      int32_t grp = -1;
+      if (lane == 0) grp = load_agent(A.gwl + gp);
+      grp = __builtin_amdgcn_readfirstlane(grp);
+      if (grp < 0) continue;  // slot reserved, id not yet stored
+      const int32_t v0 = grp << kGroupShift;
+      int32_t vv[kQ];
+#pragma unroll
+      for (int k = 0; k < kQ; ++k) {
+        const int32_t x = v0 + k * kWave + lane;
+        vv[k] = (x < A.n && (flag_byte(A.flags, x, true) & kVA)) ? x : -1;
       }
-      process_group<T, kAsync>(A, v, cnt, unused, nc);
+      process_step<T, kAsync>(A, L, vv, cnt, unused, newly, moved);
     }
-    nc = wave_sum(nc);
+    const bool any = __ballot(moved) != 0;
     if (lane == 0) {
-      if (nc)
-        __hip_atomic_fetch_add(&A.ctl->nc, nc, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_sub(&A.ctl->state, 1ull, __ATOMIC_RELEASE,
+      long long seen = 0;
+      if (any) {
+        // the sweep current now (not the claim's): changes made late in an
+        // old sweep still force a fresh full sweep
+        const long long now = (long long)((load_agent(&A.ctl->state) >> kSweepShift) & kSweepMask);
+        seen = __hip_atomic_fetch_max(&A.ctl->change_sweep, now, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+      }
+      // the watermark update must be performed before the in-flight mark drops
+      asm volatile("" ::"v"(seen) : "memory");
+      __hip_atomic_fetch_sub(&A.ctl->state, 1ull, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
     }
   }
   flush_counters<T>(A.ctl, cnt);
+  newly = wave_sum(newly);
+  if (lane == 0 && newly) atomicAdd((unsigned long long *)&A.ctl->newly, (unsigned long long)newly);
 }
 
 template <typename T, int MODE>
 __global__ void __launch_bounds__(256) k_sync_iter(RankArgs<T> A, int iter) {
   if (A.ctl->sync_done) return;
+  __shared__ WaveLds<T> lds[256 / kWave];
+  WaveLds<T> &L = lds[threadIdx.x / kWave];
   const int lane = lane_id();
   Counters cnt;
   double maxdr = 0.0;
-  long long nc = 0;
   const unsigned long long len =
       MODE == kAll ? (unsigned long long)A.n : A.sync_len[iter];
   const unsigned long long chunk = (unsigned long long)A.chunk;
@@ -453,11 +483,16 @@ __global__ void __launch_bounds__(256) k_sync_iter(RankArgs<T> A, int iter) {
     p = bcast0(p);
     if (p >= len) break;
     const unsigned long long end = p + chunk < len ? p + chunk : len;
-    for (unsigned long long g0 = p; g0 < end; g0 += kWave) {
-      const unsigned long long pos = g0 + lane;
-      int32_t v = -1;
-      if (pos < end) v = MODE == kAll ? (int32_t)pos : A.wl[pos];
-      process_group<T, MODE>(A, v, cnt, maxdr, nc);
+    for (unsigned long long g0 = p; g0 < end; g0 += kRows) {
+      int32_t vv[kQ];
+#pragma unroll
+      for (int k = 0; k < kQ; ++k) {
+        const unsigned long long pos = g0 + k * kWave + lane;
+        vv[k] = pos < end ? (MODE == kAll ? (int32_t)pos : A.wl[pos]) : -1;
+      }
+      bool unused_moved = false;
+      long long unused_newly = 0;
+      process_step<T, MODE>(A, L, vv, cnt, maxdr, unused_newly, unused_moved);
     }
   }
   maxdr = wave_max(maxdr);
@@ -474,7 +509,7 @@ __global__ void k_sync_finish(Ctl *ctl, const unsigned long long *sync_max,
   if (md <= tol || iter + 1 >= max_iters) {
     ctl->sync_done = 1;
     ctl->sync_final = iter + 1;
-    ctl->pad = md <= tol ? 1 : 0;
+    ctl->sync_conv = md <= tol ? 1 : 0;
   } else if (df) {
     sync_len[iter + 1] = ctl->tail;
   }
@@ -493,15 +528,17 @@ __global__ void k_sync_begin(Ctl *ctl, unsigned long long *sync_max,
     sync_len[0] = ctl->tail;
     ctl->sync_done = 0;
     ctl->sync_final = 0;
-    ctl->pad = 0;
+    ctl->sync_conv = 0;
     ctl->vertices = ctl->edges = ctl->out_scanned = 0;
     ctl->abort = 0;
   }
 }
 
-__global__ void k_async_begin(Ctl *ctl, int dense) {
+__global__ void k_async_begin(Ctl *ctl) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  ctl->state = dense ? kDense : 0ull;
+  ctl->state = 0ull;
+  ctl->newly = 0;
+  ctl->change_sweep = -1;
   ctl->vertices = ctl->edges = ctl->out_scanned = 0;
   ctl->abort = 0;
 }
@@ -517,11 +554,30 @@ __global__ void k_cleanup(uint32_t *flags, int32_t *wl,
   }
 }
 
+// Clears the group flags, the vertex flags of every listed group and the
+// group worklist (one thread per listed group).
+__global__ void k_cleanup_groups(uint32_t *gflags, uint32_t *flags, int32_t *gwl,
+                                 unsigned long long glen, int32_t n) {
+  const int64_t words_per_group = kGroup / 4;
+  const int64_t wmax = ((int64_t)n + 3) / 4;
+  for (unsigned long long i = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x;
+       i < glen; i += (unsigned long long)gridDim.x * blockDim.x) {
+    const int32_t grp = gwl[i];
+    gwl[i] = -1;
+    if (grp < 0) continue;
+    const int64_t w0 = (int64_t)grp * words_per_group;
+    for (int64_t k = 0; k < words_per_group && w0 + k < wmax; ++k) flags[w0 + k] = 0u;
+    reinterpret_cast<uint8_t *>(gflags)[grp] = 0;
+  }
+}
+
 __global__ void k_reset_marks(Ctl *ctl) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     ctl->tail = 0;
-    ctl->nc = 0;
+    ctl->gtail = 0;
+    ctl->change_sweep = -1;
     ctl->marked = 0;
+    ctl->newly = 0;
   }
 }
 
@@ -616,6 +672,8 @@ RankArgs<T> make_args(dfpr_graph *g, int rd, int wr) {
   A.Cw = (T *)g->C[wr];
   A.flags = g->flags;
   A.wl = g->wl;
+  A.gflags = g->gflags;
+  A.gwl = g->gwl;
   A.ctl = g->ctl;
   A.alpha = g->p.alpha;
   A.base = (1.0 - g->p.alpha) / (double)g->n;
@@ -624,7 +682,6 @@ RankArgs<T> make_args(dfpr_graph *g, int rd, int wr) {
   A.wave_min = g->p.wave_min_degree;
   A.kahan_min = g->p.kahan_min_degree;
   A.chunk = g->p.chunk;
-  A.dense_div = g->p.dense_div;
   A.max_iters = g->p.max_iters;
   A.timeout_ticks = g->p.timeout_ms > 0
                         ? (unsigned long long)g->p.timeout_ms * (unsigned long long)g->wallclock_khz
@@ -661,6 +718,23 @@ double algorithmic_bytes(const dfpr_graph *g, const Ctl &h) {
   return 8.0 * e + 36.0 * (double)h.vertices + 5.0 * (double)h.out_scanned;
 }
 
+// Rebuilds the vertex worklist from the affected flags, in vertex-id order
+// (every nonzero flag byte belongs to an affected vertex); the count lands
+// in ctl->tail on the device.  Consecutive ids keep the row, offset and
+// rank accesses of a step nearly contiguous.
+int rebuild_worklist(dfpr_graph *g) {
+  hipStream_t s = g->stream;
+  const uint8_t *fl = reinterpret_cast<const uint8_t *>(g->flags);
+  rocprim::counting_iterator<int32_t> ids(0);
+  size_t tb = 0;
+  DFPR_HIP(rocprim::select(nullptr, tb, ids, fl, g->wl, &g->ctl->tail, (size_t)g->n, s));
+  void *tmp = nullptr;
+  int rc = scratch_get(g, 14, tb, &tmp);
+  if (rc) return rc;
+  DFPR_HIP(rocprim::select(tmp, tb, ids, fl, g->wl, &g->ctl->tail, (size_t)g->n, s));
+  return DFPR_OK;
+}
+
 template <typename T>
 int run_sync(dfpr_graph *g, int mode, dfpr_stats *st) {
   hipStream_t s = g->stream;
@@ -672,6 +746,10 @@ int run_sync(dfpr_graph *g, int mode, dfpr_stats *st) {
     DFPR_HIP(hipMemcpyAsync(g->C[1 - g->cur], g->C[g->cur], (size_t)g->n * g->elem,
                             hipMemcpyDeviceToDevice, s));
   }
+  if (mode != kAll) {
+    int rc = rebuild_worklist(g);
+    if (rc) return rc;
+  }
   k_sync_begin<<<4, 256, 0, s>>>(g->ctl, g->sync_max, g->sync_grab, g->sync_len, iters);
   DFPR_HIP(hipGetLastError());
   auto kern = mode == kAll ? k_sync_iter<T, kAll> : k_sync_iter<T, kSyncDF>;
@@ -682,6 +760,10 @@ int run_sync(dfpr_graph *g, int mode, dfpr_stats *st) {
   for (; it < iters; ++it) {
     RankArgs<T> A = make_args<T>(g, (g->cur + it) & 1, (g->cur + it + 1) & 1);
     kern<<<blocks, g->p.block_size, 0, s>>>(A, it);
+    if (mode != kAll) {
+      int rc = rebuild_worklist(g);
+      if (rc) return rc;
+    }
     k_sync_finish<<<1, 64, 0, s>>>(g->ctl, g->sync_max, g->sync_len, it, g->p.tol,
                                    iters, mode == kSyncDF);
     if ((it + 1) % poll == 0 || it + 1 == iters) {
@@ -707,7 +789,7 @@ int run_sync(dfpr_graph *g, int mode, dfpr_stats *st) {
   g->last_launches = final_it;
   if (st) {
     st->sweeps = final_it;
-    st->converged = h.pad;
+    st->converged = h.sync_conv;
     st->vertices_processed = (int64_t)h.vertices;
     st->edges_gathered = (int64_t)h.edges;
     st->out_edges_scanned = (int64_t)h.out_scanned;
@@ -716,15 +798,13 @@ int run_sync(dfpr_graph *g, int mode, dfpr_stats *st) {
     (void)hipEventElapsedTime(&ms, g->ev[1], g->ev[2]);
     st->ms_kernel = ms;
   }
-  return h.pad ? DFPR_OK : DFPR_NOTCONVERGED;
+  return h.sync_conv ? DFPR_OK : DFPR_NOTCONVERGED;
 }
 
 template <typename T>
 int run_async(dfpr_graph *g, dfpr_stats *st) {
   hipStream_t s = g->stream;
-  const bool dense = g->p.dense_div > 0 &&
-                     (int64_t)g->pending_marks * g->p.dense_div > (int64_t)g->n;
-  k_async_begin<<<1, 64, 0, s>>>(g->ctl, dense ? 1 : 0);
+  k_async_begin<<<1, 64, 0, s>>>(g->ctl);
   DFPR_HIP(hipGetLastError());
   RankArgs<T> A = make_args<T>(g, g->cur, g->cur);
   const int blocks = persistent_blocks(g, k_df_async<T>);
@@ -771,6 +851,11 @@ int finish_update(dfpr_graph *g) {
   unsigned long long len = g->h_ctl->tail;
   if (len > 0)
     k_cleanup<<<grid_for((int64_t)len, g->cu_count), 256, 0, s>>>(g->flags, g->wl, len);
+  const unsigned long long glen = g->h_ctl->gtail;
+  if (glen > 0) {
+    k_cleanup_groups<<<grid_for((int64_t)glen, g->cu_count), 256, 0, s>>>(
+        g->gflags, g->flags, g->gwl, glen, g->n);
+  }
   k_reset_marks<<<1, 64, 0, s>>>(g->ctl);
   DFPR_HIP(hipGetLastError());
   g->pending_marks = 0;
@@ -861,7 +946,9 @@ int run_rank(dfpr_graph *g, int kind, dfpr_stats *st) {
     }
     if (st) {
       st->initial_marked = (int64_t)g->h_ctl->marked;
-      st->affected = (int64_t)g->h_ctl->tail;
+      st->affected = g->p.mode == DFPR_SYNC
+                         ? (int64_t)g->h_ctl->tail
+                         : (int64_t)g->h_ctl->marked + (int64_t)g->h_ctl->newly;
     }
     int rc2 = finish_update(g);
     if (rc2) return rc2;

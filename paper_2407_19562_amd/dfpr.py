@@ -16,7 +16,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libdfpr.so")
+LIB_PATH = os.environ.get("DFPR_LIB") or os.path.join(HERE, "libdfpr.so")
 
 DFPR_OK = 0
 DFPR_NOTCONVERGED = 1
@@ -49,7 +49,7 @@ class dfpr_params(ctypes.Structure):
                 ("max_iters", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("mode", ctypes.c_int32), ("kahan_min_degree", ctypes.c_int32),
                 ("wave_min_degree", ctypes.c_int32), ("chunk", ctypes.c_int32),
-                ("block_size", ctypes.c_int32), ("dense_div", ctypes.c_int32),
+                ("block_size", ctypes.c_int32),
                 ("renormalize", ctypes.c_int32), ("timeout_ms", ctypes.c_int32),
                 ("grid_blocks", ctypes.c_int32)]
 
