@@ -64,6 +64,7 @@ int check_params(const dfpr_params *p) {
   if (p->block_size < 64 || p->block_size > 256 || p->block_size % 64)
     return fail(DFPR_EINVAL, "block_size must be 64, 128, 192 or 256");
   if (p->timeout_ms < 0) return fail(DFPR_EINVAL, "timeout_ms must be >= 0");
+  if (p->reorder < 0 || p->reorder > 2) return fail(DFPR_EINVAL, "reorder must be 0, 1 or 2");
   if (p->grid_blocks < 0 || (int64_t)p->grid_blocks * (p->block_size / 64) > 32768)
     return fail(DFPR_EINVAL, "grid_blocks * waves per block must be <= 32768");
   return DFPR_OK;
@@ -76,7 +77,8 @@ static void release(dfpr_graph *g) {
                   g->in.off,  g->in.deg,  g->in.cap,  g->in.adj,
                   g->R[0],    g->R[1],    g->C[0],    g->C[1],
                   g->flags,   g->wl,      g->ctl,     g->sync_max,
-                  g->sync_grab, g->sync_len, g->gflags, g->gwl};
+                  g->sync_grab, g->sync_len, g->gflags, g->gwl,
+                  g->ext2int, g->int2ext};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (auto &s : g->scratch)
@@ -160,6 +162,7 @@ int dfpr_params_default(dfpr_params *p) {
   p->wave_min_degree = 32;
   p->chunk = 256;
   p->block_size = 256;
+  p->reorder = 0;
   p->renormalize = 0;
   p->timeout_ms = 60000;
   p->grid_blocks = 0;
@@ -306,9 +309,6 @@ int dfpr_read_ranks(const dfpr_graph *g, double *out, int mem) {
   dfpr_graph *gm = const_cast<dfpr_graph *>(g);
   if (mem == DFPR_MEM_DEVICE) {
     if ((rc = read_ranks_device(g, out))) return rc;
-  } else if (g->elem == 8) {
-    DFPR_HIP(hipMemcpyAsync(out, g->R[g->cur], (size_t)g->n * 8, hipMemcpyDeviceToHost,
-                            g->stream));
   } else {
     void *tmp = nullptr;
     if ((rc = scratch_get(gm, 13, (size_t)g->n * 8, &tmp))) return rc;
@@ -359,7 +359,11 @@ int dfpr_read_edges(const dfpr_graph *g, int dir, int32_t *src, int32_t *dst,
   DFPR_HIP(hipMemcpyAsync(deg.data(), A.deg, n * 4, hipMemcpyDeviceToHost, g->stream));
   DFPR_HIP(hipMemcpyAsync(adj.data(), A.adj, (size_t)A.adj_cap * 4, hipMemcpyDeviceToHost,
                           g->stream));
+  std::vector<int32_t> ext(g->int2ext ? n : 0);
+  if (g->int2ext)
+    DFPR_HIP(hipMemcpyAsync(ext.data(), g->int2ext, n * 4, hipMemcpyDeviceToHost, g->stream));
   DFPR_HIP(hipStreamSynchronize(g->stream));
+  auto X = [&](int64_t v) { return g->int2ext ? ext[(size_t)v] : (int32_t)v; };
   int64_t total = 0;
   for (size_t v = 0; v < n; ++v) total += deg[v];
   *count = total;
@@ -368,13 +372,13 @@ int dfpr_read_edges(const dfpr_graph *g, int dir, int32_t *src, int32_t *dst,
   int64_t k = 0;
   for (size_t v = 0; v < n; ++v) {
     for (int32_t j = 0; j < deg[v]; ++j) {
-      const int32_t w = adj[(size_t)off[v] + j];
+      const int32_t w = X(adj[(size_t)off[v] + j]);
       if (dir == DFPR_OUT) {
-        src[k] = (int32_t)v;
+        src[k] = X((int64_t)v);
         dst[k] = w;
       } else {
         src[k] = w;
-        dst[k] = (int32_t)v;
+        dst[k] = X((int64_t)v);
       }
       ++k;
     }
@@ -386,9 +390,14 @@ int dfpr_read_marks(const dfpr_graph *g, uint8_t *affected, int64_t *count) {
   if (!g) return fail(DFPR_EINVAL, "graph is NULL");
   if (affected) {
     std::vector<uint8_t> f(((size_t)g->n + 3) / 4 * 4);
+    std::vector<int32_t> ext(g->int2ext ? (size_t)g->n : 0);
     DFPR_HIP(hipMemcpyAsync(f.data(), g->flags, f.size(), hipMemcpyDeviceToHost, g->stream));
+    if (g->int2ext)
+      DFPR_HIP(hipMemcpyAsync(ext.data(), g->int2ext, (size_t)g->n * 4, hipMemcpyDeviceToHost,
+                              g->stream));
     DFPR_HIP(hipStreamSynchronize(g->stream));
-    for (int32_t v = 0; v < g->n; ++v) affected[v] = (f[v] & kVA) ? 1 : 0;
+    for (int32_t v = 0; v < g->n; ++v)
+      affected[g->int2ext ? ext[(size_t)v] : v] = (f[v] & kVA) ? 1 : 0;
   }
   if (count) {
     unsigned long long t = 0;

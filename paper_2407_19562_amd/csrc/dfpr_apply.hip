@@ -52,14 +52,22 @@ __global__ void k_validate2(int64_t m1, const int32_t *a1, const int32_t *b1,
 }
 
 // dir 0: rows are sources (out), dir 1: rows are targets (in)
+// ids are mapped to the internal order when `map` is set
 __global__ void k_batch_keys(int dir, int64_t nd, const int32_t *ds,
                              const int32_t *dd, int64_t ni, const int32_t *is,
-                             const int32_t *id, unsigned long long *keys) {
+                             const int32_t *id, const int32_t *map,
+                             unsigned long long *keys) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nd + ni;
        i += (int64_t)gridDim.x * blockDim.x) {
     const bool ins = i >= nd;
-    const uint32_t u = (uint32_t)(ins ? is[i - nd] : ds[i]);
-    const uint32_t v = (uint32_t)(ins ? id[i - nd] : dd[i]);
+    int32_t a = ins ? is[i - nd] : ds[i];
+    int32_t b = ins ? id[i - nd] : dd[i];
+    if (map) {
+      a = map[a];
+      b = map[b];
+    }
+    const uint32_t u = (uint32_t)a;
+    const uint32_t v = (uint32_t)b;
     const uint32_t row = dir == 0 ? u : v, oth = dir == 0 ? v : u;
     keys[i] = u == v ? kNoKey
                      : ((unsigned long long)row << 32 |
@@ -324,7 +332,7 @@ static int prepare_direction(dfpr_graph *g, int dir, int64_t nd,
   if ((rc = scratch_get(g, 1, m * 8, &kb))) return rc;
   if ((rc = scratch_get(g, 2, m * 8, &hr))) return rc;
   if ((rc = scratch_get(g, 3, m * 8, &sr))) return rc;
-  k_batch_keys<<<grid_for(m, cu), 256, 0, s>>>(dir, nd, ds, dd, ni, is, id,
+  k_batch_keys<<<grid_for(m, cu), 256, 0, s>>>(dir, nd, ds, dd, ni, is, id, g->ext2int,
                                                (unsigned long long *)ka);
   size_t tb = 0;
   DFPR_HIP(rocprim::radix_sort_keys(nullptr, tb, (unsigned long long *)ka,

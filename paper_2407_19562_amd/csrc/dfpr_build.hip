@@ -8,6 +8,7 @@
 // capacities get slack for in-place insertion, and the surviving keys are
 // scattered into their rows (rows end up sorted by the other endpoint).
 #include <cstring>
+#include <vector>
 
 #include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/device/device_scan.hpp>
@@ -87,6 +88,39 @@ __global__ void k_fill(int64_t m, const unsigned long long *keys,
   }
 }
 
+__global__ void k_count_src(int64_t m, const int32_t *src, int32_t *cnt) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+       i += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(cnt + src[i], 1);
+}
+
+// Sort key of vertex v: decreasing out-degree, then increasing id.
+__global__ void k_order_keys(int32_t n, const int32_t *cnt, int32_t maxdeg,
+                             unsigned long long *keys) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x)
+    keys[v] = (unsigned long long)(uint32_t)(maxdeg - cnt[v]) << 32 | (uint32_t)v;
+}
+
+__global__ void k_perm_from_keys(int32_t n, const unsigned long long *keys,
+                                 int32_t *int2ext, int32_t *ext2int) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = (int32_t)(uint32_t)keys[i];
+    int2ext[i] = v;
+    ext2int[v] = (int32_t)i;
+  }
+}
+
+__global__ void k_map_ids(int64_t m, const int32_t *map, const int32_t *a,
+                          const int32_t *b, int32_t *a2, int32_t *b2) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    a2[i] = map[a[i]];
+    b2[i] = map[b[i]];
+  }
+}
+
 inline int grid_for(int64_t work, int cu) {
   int64_t b = (work + 255) / 256;
   const int64_t lim = (int64_t)cu * 16;
@@ -114,6 +148,45 @@ int build_graph(dfpr_graph *g, int64_t m, const int32_t *src,
   const size_t mk = (size_t)(m > 0 ? m : 1);
   void *keys_a, *keys_b, *rank, *tmp;
   int rc;
+
+  // Internal order: decreasing out-degree (an ordering heuristic, so the
+  // raw input counts, duplicates included, are good enough).  The hot
+  // contributions of a power-law graph then sit in few cache lines.
+  if (g->p.reorder != 0 && m > 0) {
+    int32_t *cnt;
+    if ((rc = scratch_get(g, 2, (size_t)n * 4, (void **)&cnt))) return rc;
+    DFPR_HIP(hipMemsetAsync(cnt, 0, (size_t)n * 4, s));
+    k_count_src<<<grid_for(m, cu), 256, 0, s>>>(m, src, cnt);
+    std::vector<int32_t> hc((size_t)n);
+    DFPR_HIP(hipMemcpyAsync(hc.data(), cnt, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+    DFPR_HIP(hipStreamSynchronize(s));
+    int32_t maxdeg = 0;
+    for (int32_t x : hc) maxdeg = x > maxdeg ? x : maxdeg;
+    const double mean = (double)m / (double)n;
+    if (g->p.reorder == 1 || (double)maxdeg >= 8.0 * mean) {
+      if ((rc = scratch_get(g, 0, (size_t)n * 8, &keys_a))) return rc;
+      if ((rc = scratch_get(g, 1, (size_t)n * 8, &keys_b))) return rc;
+      k_order_keys<<<grid_for(n, cu), 256, 0, s>>>(n, cnt, maxdeg,
+                                                   (unsigned long long *)keys_a);
+      size_t tb = 0;
+      DFPR_HIP(rocprim::radix_sort_keys(nullptr, tb, (unsigned long long *)keys_a,
+                                        (unsigned long long *)keys_b, (size_t)n, 0, 64, s));
+      if ((rc = scratch_get(g, 5, tb, &tmp))) return rc;
+      DFPR_HIP(rocprim::radix_sort_keys(tmp, tb, (unsigned long long *)keys_a,
+                                        (unsigned long long *)keys_b, (size_t)n, 0, 64, s));
+      DFPR_HIP(hipMalloc(&g->ext2int, (size_t)n * 4));
+      DFPR_HIP(hipMalloc(&g->int2ext, (size_t)n * 4));
+      k_perm_from_keys<<<grid_for(n, cu), 256, 0, s>>>(n, (unsigned long long *)keys_b,
+                                                       g->int2ext, g->ext2int);
+      int32_t *ms, *md;
+      if ((rc = scratch_get(g, 6, mk * 4, (void **)&ms))) return rc;
+      if ((rc = scratch_get(g, 7, mk * 4, (void **)&md))) return rc;
+      k_map_ids<<<grid_for(m, cu), 256, 0, s>>>(m, g->ext2int, src, dst, ms, md);
+      DFPR_HIP(hipGetLastError());
+      src = ms;
+      dst = md;
+    }
+  }
   if ((rc = scratch_get(g, 0, mk * 8, &keys_a))) return rc;
   if ((rc = scratch_get(g, 1, mk * 8, &keys_b))) return rc;
   if ((rc = scratch_get(g, 2, mk * 8, &rank))) return rc;
@@ -195,7 +268,7 @@ int build_graph(dfpr_graph *g, int64_t m, const int32_t *src,
   }
   g->m = stored;
   // the build scratch is large; give it back
-  for (int i = 0; i < 6; ++i) {
+  for (int i = 0; i < 8; ++i) {
     if (g->scratch[i].p) (void)hipFree(g->scratch[i].p);
     g->scratch[i].p = nullptr;
     g->scratch[i].bytes = 0;

@@ -113,6 +113,8 @@ struct dfpr_graph {
   int32_t ngroups = 0;
   uint32_t *gflags = nullptr;  // [ngroups] bytes
   int32_t *gwl = nullptr;      // group worklist [ngroups], unused slots -1
+  int32_t *ext2int = nullptr;  // caller id -> internal id (null: identity)
+  int32_t *int2ext = nullptr;  // internal id -> caller id
   dfpr::Ctl *ctl = nullptr;
   dfpr::Ctl *h_ctl = nullptr;           // pinned host mirror
   unsigned long long *sync_max = nullptr;   // [kMaxIters] bit patterns

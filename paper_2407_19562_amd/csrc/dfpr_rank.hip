@@ -621,6 +621,24 @@ __global__ void k_scale(int32_t n, const int32_t *out_deg, const double *sum,
   }
 }
 
+// Ranks in the caller's id order <-> the internal order (int2ext may be
+// null: identity).
+template <typename T>
+__global__ void k_ranks_in(int32_t n, const int32_t *int2ext, const double *ext,
+                           T *R) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    R[i] = (T)ext[int2ext ? int2ext[i] : i];
+}
+
+template <typename T>
+__global__ void k_ranks_out(int32_t n, const int32_t *int2ext, const T *R,
+                            double *ext) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    ext[int2ext ? int2ext[i] : i] = (double)R[i];
+}
+
 __global__ void k_f32_to_f64(int32_t n, const float *a, double *b) {
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
        v += (int64_t)gridDim.x * blockDim.x)
@@ -807,7 +825,16 @@ int run_async(dfpr_graph *g, dfpr_stats *st) {
   k_async_begin<<<1, 64, 0, s>>>(g->ctl);
   DFPR_HIP(hipGetLastError());
   RankArgs<T> A = make_args<T>(g, g->cur, g->cur);
-  const int blocks = persistent_blocks(g, k_df_async<T>);
+  // At most one wavefront per listed group: with more, idle wavefronts
+  // would start new sweeps over groups still being processed and a sweep
+  // would stop meaning one pass over the affected groups.
+  DFPR_HIP(hipMemcpyAsync(g->h_ctl, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+  DFPR_HIP(hipStreamSynchronize(s));
+  const int waves_per_block = g->p.block_size / kWave;
+  int blocks = persistent_blocks(g, k_df_async<T>);
+  const long long groups = (long long)g->h_ctl->gtail;
+  const long long want = (groups + waves_per_block - 1) / waves_per_block;
+  if (want < blocks) blocks = (int)(want > 0 ? want : 1);
   DFPR_HIP(hipEventRecord(g->ev[1], s));
   k_df_async<T><<<blocks, g->p.block_size, 0, s>>>(A);
   DFPR_HIP(hipGetLastError());
@@ -892,24 +919,23 @@ int refresh_contributions(dfpr_graph *g) {
 
 int set_ranks_device(dfpr_graph *g, const double *r) {
   hipStream_t s = g->stream;
-  if (g->elem == 8) {
-    DFPR_HIP(hipMemcpyAsync(g->R[g->cur], r, (size_t)g->n * 8, hipMemcpyDeviceToDevice, s));
-  } else {
-    k_f64_to_f32<<<grid_for(g->n, g->cu_count), 256, 0, s>>>(g->n, r, (float *)g->R[g->cur]);
-    DFPR_HIP(hipGetLastError());
-  }
+  const int b = grid_for(g->n, g->cu_count);
+  if (g->elem == 8)
+    k_ranks_in<double><<<b, 256, 0, s>>>(g->n, g->int2ext, r, (double *)g->R[g->cur]);
+  else
+    k_ranks_in<float><<<b, 256, 0, s>>>(g->n, g->int2ext, r, (float *)g->R[g->cur]);
+  DFPR_HIP(hipGetLastError());
   return refresh_contributions(g);
 }
 
 int read_ranks_device(const dfpr_graph *g, double *out) {
   hipStream_t s = g->stream;
-  if (g->elem == 8) {
-    DFPR_HIP(hipMemcpyAsync(out, g->R[g->cur], (size_t)g->n * 8, hipMemcpyDeviceToDevice, s));
-  } else {
-    k_f32_to_f64<<<grid_for(g->n, g->cu_count), 256, 0, s>>>(g->n, (const float *)g->R[g->cur],
-                                                             out);
-    DFPR_HIP(hipGetLastError());
-  }
+  const int b = grid_for(g->n, g->cu_count);
+  if (g->elem == 8)
+    k_ranks_out<double><<<b, 256, 0, s>>>(g->n, g->int2ext, (const double *)g->R[g->cur], out);
+  else
+    k_ranks_out<float><<<b, 256, 0, s>>>(g->n, g->int2ext, (const float *)g->R[g->cur], out);
+  DFPR_HIP(hipGetLastError());
   return DFPR_OK;
 }
 

@@ -49,7 +49,7 @@ class dfpr_params(ctypes.Structure):
                 ("max_iters", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("mode", ctypes.c_int32), ("kahan_min_degree", ctypes.c_int32),
                 ("wave_min_degree", ctypes.c_int32), ("chunk", ctypes.c_int32),
-                ("block_size", ctypes.c_int32),
+                ("block_size", ctypes.c_int32), ("reorder", ctypes.c_int32),
                 ("renormalize", ctypes.c_int32), ("timeout_ms", ctypes.c_int32),
                 ("grid_blocks", ctypes.c_int32)]
 

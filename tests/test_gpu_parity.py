@@ -60,9 +60,10 @@ def graph(D, n, s, d, **kw):
 
 # --- structure ------------------------------------------------------------------
 
+@pytest.mark.parametrize("reorder", [0, 1])
 @pytest.mark.parametrize("case", ["rmat_small", "ragged", "tiny", "empty"])
-def test_structure_roundtrip(D, O, case):
-    say("structure", case)
+def test_structure_roundtrip(D, O, case, reorder):
+    say("structure", case, reorder)
     if case == "rmat_small":
         n, s, d = inputs.rmat_small()
     elif case == "ragged":
@@ -75,7 +76,7 @@ def test_structure_roundtrip(D, O, case):
     else:
         n, s, d = 5, np.empty(0, np.int32), np.empty(0, np.int32)
     ref = O.edge_set(n, s, d)
-    with graph(D, n, s, d) as g:
+    with graph(D, n, s, d, reorder=reorder) as g:
         assert g.size() == (n, ref.size)
         for direction in (D.DFPR_OUT, D.DFPR_IN):
             gs, gd = g.edges(direction)
@@ -162,15 +163,16 @@ def test_marking_frontier_example(D, O):
         assert cnt == 5
 
 
-def test_marking_matches_oracle_rmat(D, O):
-    say("marking rmat")
+@pytest.mark.parametrize("reorder", [0, 1])
+def test_marking_matches_oracle_rmat(D, O, reorder):
+    say("marking rmat", reorder)
     n, s, d = inputs.rmat_small()
     b = inputs.batches(n, s, d, 1, 1001, frac=1e-3)[0]
     R, _, _ = O.pagerank(n, s, d)
     ns, nd, dt, it = O.apply_batch(n, s, d, b.del_src, b.del_dst, b.ins_src, b.ins_dst)
     src = np.concatenate([dt // n, it // n]).astype(np.int32)
     ref = O.df_bb(n, (s, d), (ns, nd), src, R, max_iters=0)
-    with graph(D, n, s, d) as g:
+    with graph(D, n, s, d, reorder=reorder) as g:
         g.apply(b)
         aff, cnt = g.marks()
         assert np.array_equal(aff, ref.affected)
@@ -195,17 +197,18 @@ def test_static_matches_oracle(D, O, prec):
         assert rel32(R, ref) < FP32_REL
 
 
+@pytest.mark.parametrize("reorder", [0, 2])
 @pytest.mark.parametrize("mode", ["sync", "async"])
 @pytest.mark.parametrize("frac", [1e-3, 1e-2])
-def test_df_fp64_matches_oracle(D, O, mode, frac):
-    say("df fp64", mode, frac)
+def test_df_fp64_matches_oracle(D, O, mode, frac, reorder):
+    say("df fp64", mode, frac, reorder)
     n, s, d = inputs.rmat_small()
     R0, _, _ = O.pagerank(n, s, d)
     b = inputs.batches(n, s, d, 1, 1001, frac=frac)[0]
     ns, nd, res, ndel, nins = O.update(n, s, d, b, R0)
     ref, _, _ = O.pagerank(n, ns, nd)
     m = D.DFPR_SYNC if mode == "sync" else D.DFPR_ASYNC
-    with graph(D, n, s, d, mode=m) as g:
+    with graph(D, n, s, d, mode=m, reorder=reorder) as g:
         g.set_ranks(R0)                        # parity mode: R^{t-1} exact
         assert g.apply(b) == (ndel, nins)
         rc, st = g.update()
