@@ -32,6 +32,7 @@
 //                device so the host only polls every few iterations.
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include <rocprim/device/device_select.hpp>
 #include <rocprim/iterator/counting_iterator.hpp>
@@ -342,7 +343,8 @@ __device__ __forceinline__ void flush_counters(Ctl *ctl, Counters &c) {
 // is 0 and no change is left to propagate.  Otherwise the next sweep
 // starts at once, without waiting for claims still held (no barrier).
 template <typename T>
-__device__ void sweep_end(const RankArgs<T> &A, unsigned long long W) {
+__device__ void sweep_end(const RankArgs<T> &A, unsigned long long W,
+                          int *done_count) {
   unsigned long long *st = &A.ctl->state;
   const unsigned long long bound = load_agent(&A.ctl->gtail);
   const unsigned long long cur = (W >> kCursorShift) & kCursorMask;
@@ -358,7 +360,7 @@ __device__ void sweep_end(const RankArgs<T> &A, unsigned long long W) {
     else
       nw = (ns << kSweepShift) | inflight;
   } else if (inflight == 0) {
-    // confirm once with acquire ordering before ending the launch
+    // confirm once with acquire ordering before ending the graph's update
     if (__hip_atomic_load(st, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != W) return;
     if (load_agent(&A.ctl->change_sweep) >= (long long)sweep) return;
     nw = kDone | ((sweep + 1) << kSweepShift);
@@ -366,104 +368,183 @@ __device__ void sweep_end(const RankArgs<T> &A, unsigned long long W) {
     return;
   }
   unsigned long long expect = W;
-  __hip_atomic_compare_exchange_strong(st, &expect, nw, __ATOMIC_RELAXED,
-                                       __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
+  const bool won = __hip_atomic_compare_exchange_strong(
+      st, &expect, nw, __ATOMIC_RELAXED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (won && (nw & kDone) && done_count) atomicAdd(done_count, 1);
 }
 
-// The lock-free persistent kernel.  A claim takes `chunk / 256` positions of
-// the group worklist (at least one); each affected vertex of a claimed group
-// is recomputed in place.
+enum StepResult { kWorked = 0, kNoWork = 1, kGraphDone = 2 };
+
+// One scheduling step of the lock-free scheme on one graph: claim
+// `per` positions of its group worklist and recompute every affected vertex
+// of those groups in place.  A graph never gets more claim holders than it
+// has listed groups; beyond that, extra wavefronts would only start new
+// sweeps over groups still being processed.
+template <typename T>
+__device__ int df_async_step(const RankArgs<T> &A, WaveLds<T> &L, Counters &cnt,
+                             long long &newly, unsigned long long per,
+                             int *done_count) {
+  const int lane = lane_id();
+  const unsigned long long grab = (per << kCursorShift) | 1ull;
+  unsigned long long W = 0, gt = 0;
+  if (lane == 0) {
+    W = load_agent(&A.ctl->state);
+    gt = load_agent(&A.ctl->gtail);
+  }
+  W = bcast0(W);
+  gt = bcast0(gt);
+  if (W & kDone) return kGraphDone;
+  if (((W >> kCursorShift) & kCursorMask) >= gt) {
+    if (lane == 0) sweep_end(A, W, done_count);
+    return kNoWork;
+  }
+  if ((W & kInflightMask) >= gt) return kNoWork;
+  unsigned long long W2 = 0;
+  if (lane == 0) {
+    W2 = __hip_atomic_fetch_add(&A.ctl->state, grab, __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_AGENT);
+    gt = load_agent(&A.ctl->gtail);
+  }
+  W2 = bcast0(W2);
+  gt = bcast0(gt);
+  if (W2 & kDone) return kGraphDone;
+  const unsigned long long p = (W2 >> kCursorShift) & kCursorMask;
+  if (p >= gt) {
+    if (lane == 0)
+      __hip_atomic_fetch_sub(&A.ctl->state, 1ull, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    return kNoWork;
+  }
+  const unsigned long long end = p + per < gt ? p + per : gt;
+  bool moved = false;
+  double unused = 0.0;
+  for (unsigned long long gp = p; gp < end; ++gp) {
+    int32_t grp = -1;
+    if (lane == 0) grp = load_agent(A.gwl + gp);
+    grp = __builtin_amdgcn_readfirstlane(grp);
+    if (grp < 0) continue;  // slot reserved, id not yet stored
+    const int32_t v0 = grp << kGroupShift;
+    int32_t vv[kQ];
+#pragma unroll
+    for (int k = 0; k < kQ; ++k) {
+      const int32_t x = v0 + k * kWave + lane;
+      vv[k] = (x < A.n && (flag_byte(A.flags, x, true) & kVA)) ? x : -1;
+    }
+    process_step<T, kAsync>(A, L, vv, cnt, unused, newly, moved);
+  }
+  const bool any = __ballot(moved) != 0;
+  if (lane == 0) {
+    long long seen = 0;
+    if (any) {
+      // the sweep current now (not the claim's): changes made late in an
+      // old sweep still force a fresh full sweep
+      const long long now =
+          (long long)((load_agent(&A.ctl->state) >> kSweepShift) & kSweepMask);
+      seen = __hip_atomic_fetch_max(&A.ctl->change_sweep, now, __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // the watermark update must be performed before the in-flight mark drops
+    asm volatile("" ::"v"(seen) : "memory");
+    __hip_atomic_fetch_sub(&A.ctl->state, 1ull, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+  }
+  return kWorked;
+}
+
+template <typename T>
+__device__ __forceinline__ void flush_graph(Ctl *ctl, Counters &cnt,
+                                            long long &newly) {
+  flush_counters<T>(ctl, cnt);
+  newly = wave_sum(newly);
+  if (lane_id() == 0 && newly)
+    atomicAdd((unsigned long long *)&ctl->newly, (unsigned long long)newly);
+  cnt = Counters();
+  newly = 0;
+}
+
+__device__ __forceinline__ unsigned long long groups_per_claim(int chunk) {
+  // at least one so the cursor always advances
+  return chunk >= kGroup ? (unsigned long long)(chunk / kGroup) : 1ull;
+}
+
+// The lock-free persistent kernel for one graph.
 template <typename T>
 __global__ void __launch_bounds__(256) k_df_async(RankArgs<T> A) {
   __shared__ WaveLds<T> lds[256 / kWave];
   WaveLds<T> &L = lds[threadIdx.x / kWave];
   const int lane = lane_id();
   Counters cnt;
-  const unsigned long long t_start = wall_clock64();
-  // groups per claim; at least one so the cursor always advances
-  const unsigned long long per =
-      A.chunk >= kGroup ? (unsigned long long)(A.chunk / kGroup) : 1ull;
-  const unsigned long long grab = (per << kCursorShift) | 1ull;
-  unsigned polls = 0;
-  double unused = 0.0;
   long long newly = 0;
+  const unsigned long long t_start = wall_clock64();
+  const unsigned long long per = groups_per_claim(A.chunk);
+  unsigned polls = 0;
   while (true) {
-    unsigned long long W = 0;
     int ab = 0;
-    if (lane == 0) {
-      W = load_agent(&A.ctl->state);
-      if ((++polls & 15u) == 0) ab = load_agent(&A.ctl->abort);
-    }
-    W = bcast0(W);
-    ab = __builtin_amdgcn_readfirstlane(ab);
-    if ((W & kDone) || ab) break;
-    unsigned long long gt = 0;
-    if (lane == 0) gt = load_agent(&A.ctl->gtail);
-    gt = bcast0(gt);
-    if (((W >> kCursorShift) & kCursorMask) >= gt) {
-      if (lane == 0) sweep_end(A, W);
+    if (lane == 0 && (++polls & 15u) == 0) ab = load_agent(&A.ctl->abort);
+    if (__builtin_amdgcn_readfirstlane(ab)) break;
+    const int r = df_async_step<T>(A, L, cnt, newly, per, nullptr);
+    if (r == kGraphDone) break;
+    if (r == kNoWork) {
       __builtin_amdgcn_s_sleep(32);
-      if (A.timeout_ticks && ((polls & 63u) == 0)) {
-        const bool late = wall_clock64() - t_start > A.timeout_ticks;
-        if (late) {
-          if (lane == 0) store_agent(&A.ctl->abort, 1);
-          break;
-        }
+      if (A.timeout_ticks && ((polls & 63u) == 0) &&
+          wall_clock64() - t_start > A.timeout_ticks) {
+        if (lane == 0) store_agent(&A.ctl->abort, 1);
+        break;
       }
-      continue;
-    }
-    unsigned long long W2 = 0;
-    if (lane == 0) {
-      W2 = __hip_atomic_fetch_add(&A.ctl->state, grab, __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_AGENT);
-      gt = load_agent(&A.ctl->gtail);
-    }
-    W2 = bcast0(W2);
-    gt = bcast0(gt);
-    if (W2 & kDone) break;
-    const unsigned long long p = (W2 >> kCursorShift) & kCursorMask;
-    if (p >= gt) {
-      if (lane == 0)
-        __hip_atomic_fetch_sub(&A.ctl->state, 1ull, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-      continue;
-    }
-    const unsigned long long end = p + per < gt ? p + per : gt;
-    bool moved = false;
-    for (unsigned long long gp = p; gp < end; ++gp) {
-      int32_t grp = -1;
-      if (lane == 0) grp = load_agent(A.gwl + gp);
-      grp = __builtin_amdgcn_readfirstlane(grp);
-      if (grp < 0) continue;  // slot reserved, id not yet stored
-      const int32_t v0 = grp << kGroupShift;
-      int32_t vv[kQ];
-#pragma unroll
-      for (int k = 0; k < kQ; ++k) {
-        const int32_t x = v0 + k * kWave + lane;
-        vv[k] = (x < A.n && (flag_byte(A.flags, x, true) & kVA)) ? x : -1;
-      }
-      process_step<T, kAsync>(A, L, vv, cnt, unused, newly, moved);
-    }
-    const bool any = __ballot(moved) != 0;
-    if (lane == 0) {
-      long long seen = 0;
-      if (any) {
-        // the sweep current now (not the claim's): changes made late in an
-        // old sweep still force a fresh full sweep
-        const long long now = (long long)((load_agent(&A.ctl->state) >> kSweepShift) & kSweepMask);
-        seen = __hip_atomic_fetch_max(&A.ctl->change_sweep, now, __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_AGENT);
-      }
-      // the watermark update must be performed before the in-flight mark drops
-      asm volatile("" ::"v"(seen) : "memory");
-      __hip_atomic_fetch_sub(&A.ctl->state, 1ull, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
     }
   }
-  flush_counters<T>(A.ctl, cnt);
-  newly = wave_sum(newly);
-  if (lane == 0 && newly) atomicAdd((unsigned long long *)&A.ctl->newly, (unsigned long long)newly);
+  flush_graph<T>(A.ctl, cnt, newly);
+}
+
+// The lock-free persistent kernel for many graphs at once: each wavefront
+// works on one graph until it finds nothing to claim there, then moves to
+// the next; the launch ends when every graph's update has ended.
+template <typename T>
+__global__ void __launch_bounds__(256) k_df_async_many(const RankArgs<T> *descs,
+                                                       int count, int *done_count,
+                                                       int *abort_flag,
+                                                       unsigned long long timeout_ticks) {
+  __shared__ WaveLds<T> lds[256 / kWave];
+  WaveLds<T> &L = lds[threadIdx.x / kWave];
+  const int lane = lane_id();
+  const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  int gi = (int)(wave % count);
+  RankArgs<T> A = descs[gi];
+  unsigned long long per = groups_per_claim(A.chunk);
+  Counters cnt;
+  long long newly = 0;
+  const unsigned long long t_start = wall_clock64();
+  int idle = 0;
+  unsigned polls = 0;
+  while (true) {
+    int dc = 0, ab = 0;
+    if (lane == 0) {
+      dc = load_agent(done_count);
+      if ((++polls & 15u) == 0) ab = load_agent(abort_flag);
+    }
+    dc = __builtin_amdgcn_readfirstlane(dc);
+    ab = __builtin_amdgcn_readfirstlane(ab);
+    if (dc >= count || ab) break;
+    const int r = df_async_step<T>(A, L, cnt, newly, per, done_count);
+    if (r == kWorked) {
+      idle = 0;
+      continue;
+    }
+    // nothing to claim here: move on (a full lap without work backs off)
+    flush_graph<T>(A.ctl, cnt, newly);
+    gi = gi + 1 < count ? gi + 1 : 0;
+    A = descs[gi];
+    per = groups_per_claim(A.chunk);
+    if (++idle >= count) {
+      idle = 0;
+      __builtin_amdgcn_s_sleep(32);
+      if (timeout_ticks && wall_clock64() - t_start > timeout_ticks) {
+        if (lane == 0) store_agent(abort_flag, 1);
+        break;
+      }
+    }
+  }
+  flush_graph<T>(A.ctl, cnt, newly);
 }
 
 template <typename T, int MODE>
@@ -568,6 +649,78 @@ __global__ void k_cleanup_groups(uint32_t *gflags, uint32_t *flags, int32_t *gwl
     const int64_t w0 = (int64_t)grp * words_per_group;
     for (int64_t k = 0; k < words_per_group && w0 + k < wmax; ++k) flags[w0 + k] = 0u;
     reinterpret_cast<uint8_t *>(gflags)[grp] = 0;
+  }
+}
+
+// Per-graph summary of the control block, gathered for many graphs at once.
+struct Summary {
+  unsigned long long state, tail, gtail, vertices, edges, out_scanned;
+  long long marked, newly;
+  int abort, pad;
+};
+
+template <typename T>
+__global__ void k_gather_summary(const RankArgs<T> *descs, int count, Summary *out) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+    const Ctl *c = descs[i].ctl;
+    Summary s;
+    s.state = c->state;
+    s.tail = c->tail;
+    s.gtail = c->gtail;
+    s.vertices = c->vertices;
+    s.edges = c->edges;
+    s.out_scanned = c->out_scanned;
+    s.marked = c->marked;
+    s.newly = c->newly;
+    s.abort = c->abort;
+    s.pad = 0;
+    out[i] = s;
+  }
+}
+
+template <typename T>
+__global__ void k_begin_many(const RankArgs<T> *descs, int count, int *done_count) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+    Ctl *c = descs[i].ctl;
+    c->state = 0ull;
+    c->newly = 0;
+    c->change_sweep = -1;
+    c->abort = 0;
+    c->vertices = c->edges = c->out_scanned = 0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *done_count = 0;
+}
+
+// One workgroup per graph: clears the flags and worklists the update used.
+template <typename T>
+__global__ void k_cleanup_many(const RankArgs<T> *descs, int count) {
+  for (int i = blockIdx.x; i < count; i += gridDim.x) {
+    const RankArgs<T> &A = descs[i];
+    Ctl *c = A.ctl;
+    const unsigned long long len = c->tail, glen = c->gtail;
+    for (unsigned long long k = threadIdx.x; k < len; k += blockDim.x) {
+      const int32_t v = A.wl[k];
+      if (v >= 0) reinterpret_cast<uint8_t *>(A.flags)[v] = 0;
+      A.wl[k] = -1;
+    }
+    const int64_t wmax = ((int64_t)A.n + 3) / 4;
+    for (unsigned long long k = threadIdx.x; k < glen; k += blockDim.x) {
+      const int32_t grp = A.gwl[k];
+      A.gwl[k] = -1;
+      if (grp < 0) continue;
+      const int64_t w0 = (int64_t)grp * (kGroup / 4);
+      for (int64_t q = 0; q < kGroup / 4 && w0 + q < wmax; ++q) A.flags[w0 + q] = 0u;
+      reinterpret_cast<uint8_t *>(A.gflags)[grp] = 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      c->tail = 0;
+      c->gtail = 0;
+      c->change_sweep = -1;
+      c->marked = 0;
+      c->newly = 0;
+    }
+    __syncthreads();
   }
 }
 
@@ -990,6 +1143,121 @@ int run_rank(dfpr_graph *g, int kind, dfpr_stats *st) {
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, g->ev[0], g->ev[3]);
     st->ms = ms;
+  }
+  return rc;
+}
+
+namespace {
+
+template <typename T>
+int update_many_t(dfpr_graph *const *gs, int32_t count, dfpr_stats *stats) {
+  std::vector<dfpr_graph *> act;
+  for (int32_t i = 0; i < count; ++i) {
+    if (stats) {
+      stats[i] = dfpr_stats{};
+      stats[i].converged = 1;
+    }
+    if (gs[i]->pending_marks > 0) act.push_back(gs[i]);
+  }
+  if (act.empty()) return DFPR_OK;
+  dfpr_graph *g0 = act[0];
+  hipStream_t s = g0->stream;
+  for (dfpr_graph *g : act)
+    if (g->stream != s) DFPR_HIP(hipStreamSynchronize(g->stream));
+  const int na = (int)act.size();
+  std::vector<RankArgs<T>> h(na);
+  for (int i = 0; i < na; ++i) h[i] = make_args<T>(act[i], act[i]->cur, act[i]->cur);
+  // device copies: descriptors, summaries, the done counter
+  const size_t dbytes = sizeof(RankArgs<T>) * na;
+  const size_t sbytes = sizeof(Summary) * na;
+  void *buf = nullptr;
+  int rc = scratch_get(g0, 12, dbytes + sbytes + 256, &buf);
+  if (rc) return rc;
+  RankArgs<T> *d_desc = (RankArgs<T> *)buf;
+  Summary *d_sum = (Summary *)((char *)buf + dbytes);
+  int *d_done = (int *)((char *)buf + dbytes + sbytes + 128);
+  DFPR_HIP(hipMemcpyAsync(d_desc, h.data(), dbytes, hipMemcpyHostToDevice, s));
+  const int gb = grid_for(na, g0->cu_count);
+  k_begin_many<T><<<gb, 256, 0, s>>>(d_desc, na, d_done);
+  k_gather_summary<T><<<gb, 256, 0, s>>>(d_desc, na, d_sum);
+  std::vector<Summary> hs(na);
+  DFPR_HIP(hipMemcpyAsync(hs.data(), d_sum, sbytes, hipMemcpyDeviceToHost, s));
+  DFPR_HIP(hipStreamSynchronize(s));
+  long long groups = 0;
+  for (const Summary &x : hs) groups += (long long)x.gtail;
+  const int wpb = g0->p.block_size / kWave;
+  int blocks = persistent_blocks(g0, k_df_async_many<T>);
+  const long long want = (groups + wpb - 1) / wpb;
+  if (want < blocks) blocks = (int)(want > 0 ? want : 1);
+  const unsigned long long ticks =
+      g0->p.timeout_ms > 0 ? (unsigned long long)g0->p.timeout_ms * (unsigned long long)g0->wallclock_khz
+                           : 0ull;
+  DFPR_HIP(hipEventRecord(g0->ev[0], s));
+  k_df_async_many<T><<<blocks, g0->p.block_size, 0, s>>>(d_desc, na, d_done, &g0->ctl->abort,
+                                                         ticks);
+  DFPR_HIP(hipGetLastError());
+  DFPR_HIP(hipEventRecord(g0->ev[1], s));
+  k_gather_summary<T><<<gb, 256, 0, s>>>(d_desc, na, d_sum);
+  DFPR_HIP(hipMemcpyAsync(hs.data(), d_sum, sbytes, hipMemcpyDeviceToHost, s));
+  k_cleanup_many<T><<<na < g0->cu_count * 8 ? na : g0->cu_count * 8, 256, 0, s>>>(d_desc, na);
+  DFPR_HIP(hipGetLastError());
+  DFPR_HIP(hipStreamSynchronize(s));
+  float kms = 0.f;
+  (void)hipEventElapsedTime(&kms, g0->ev[0], g0->ev[1]);
+  int worst = DFPR_OK;
+  bool aborted = false;
+  for (int i = 0, j = 0; i < count; ++i) {
+    if (gs[i]->pending_marks <= 0) continue;
+    dfpr_graph *g = gs[i];
+    const Summary &x = hs[j++];
+    Ctl c{};
+    c.vertices = x.vertices;
+    c.edges = x.edges;
+    c.out_scanned = x.out_scanned;
+    g->last_bytes = algorithmic_bytes(g, c);
+    g->last_launches = 1;
+    g->pending_marks = 0;
+    const bool capped = (x.state & kCapped) != 0;
+    aborted = aborted || x.abort;
+    if (capped && worst == DFPR_OK) worst = DFPR_NOTCONVERGED;
+    if (stats) {
+      dfpr_stats &st = stats[i];
+      st.sweeps = (int)((x.state >> kSweepShift) & kSweepMask);
+      st.converged = !capped && !x.abort;
+      st.initial_marked = x.marked;
+      st.affected = x.marked + x.newly;
+      st.vertices_processed = (long long)x.vertices;
+      st.edges_gathered = (long long)x.edges;
+      st.out_edges_scanned = (long long)x.out_scanned;
+      st.max_delta = -1.0;
+      st.ms_kernel = kms;
+      st.ms = kms;
+    }
+    if (g->elem == 4 && g->p.renormalize) {
+      int r2 = renormalize<float>(g);
+      if (r2) return r2;
+    }
+  }
+  if (aborted) return fail(DFPR_EABORT, "batched persistent kernel watchdog fired");
+  return worst;
+}
+
+}  // namespace
+
+int update_many(dfpr_graph *const *gs, int32_t count, dfpr_stats *stats) {
+  if (count == 0) return DFPR_OK;
+  const int elem = gs[0]->elem;
+  const int dev = gs[0]->device;
+  for (int32_t i = 0; i < count; ++i) {
+    if (gs[i]->elem != elem) return fail(DFPR_EINVAL, "graphs mix fp32 and fp64 ranks");
+    if (gs[i]->device != dev) return fail(DFPR_EINVAL, "graphs live on different devices");
+    for (int32_t j = 0; j < i; ++j)
+      if (gs[j] == gs[i]) return fail(DFPR_EINVAL, "a graph appears twice");
+  }
+  int rc = elem == 8 ? update_many_t<double>(gs, count, stats)
+                     : update_many_t<float>(gs, count, stats);
+  if (rc >= 0 && elem == 4) {
+    for (int32_t i = 0; i < count; ++i) DFPR_HIP(hipStreamSynchronize(gs[i]->stream));
   }
   return rc;
 }
