@@ -1,21 +1,24 @@
 """Benchmark: Dynamic Frontier PageRank updates on one MI355X.
 
-Workload (default): R-MAT graph with 2^22 vertices and 16 * 2^22 =
-67,108,864 edges (a=0.57, b=c=0.19, seed 2), ranks from the GPU static
-PageRank, then update batches of 1e-3 * |E| edges (80% insertions of
-non-edges, 20% deletions of edges; seed 2020) applied one after another.
-One step = apply one batch in place + one DF update (fp64, lock-free
-persistent kernel by default).  Batches are resident in device memory
-before the timed region.
+Default workload (the headline line): R-MAT graph with 2^22 vertices and
+16 * 2^22 = 67,108,864 edges (a=0.57, b=c=0.19, seed 2), ranks from the
+GPU static PageRank, then update batches of 1e-3 * |E| edges (80%
+insertions of non-edges, 20% deletions of edges; seed 2020) applied one
+after another.  One step = apply one batch in place + one DF update (fp64).
+Batches are resident in device memory before the timed region.
 
-Prints one JSON line with the metric, the roofline of the rank kernel
-(algorithmic bytes counted by the library / kernel time from HIP events on
-the library's stream) and the fp64 CPU oracle timed on this host.
+Other workloads (one JSON line each): `sweep` (batch sizes 1e-7..1e-1 |E|
+on the same R-MAT, DF vs static recompute, fp64 and fp32), `grid4096`
+(4096x4096 road-like grid, lock-free vs synchronous, fp64 and fp32),
+`batched1024` (1024 small graphs in one launch vs one by one), `serving`
+(resident graphs under a Poisson stream of batches), `rmat14` (small R-MAT).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
+import math
 import os
 import statistics
 import sys
@@ -30,6 +33,7 @@ METRIC = ("update latency ms/batch + edges-processed/s & HBM GB/s; "
           "p50/p99 served latency")
 PEAK_HBM_GBS = 8000.0
 FRACS = [1e-7, 1e-5, 1e-3, 1e-1]
+MODES = {"sync": 1, "async": 0}
 
 
 def log(*a):
@@ -42,22 +46,34 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat22",
-                    choices=["rmat22", "rmat14", "grid4096"])
+                    choices=["rmat22", "rmat14", "sweep", "grid4096",
+                             "batched1024", "serving"])
     ap.add_argument("--frac", type=float, default=1e-3)
     ap.add_argument("--precision", type=int, default=64, choices=[32, 64])
-    ap.add_argument("--mode", default="async", choices=["async", "sync"])
+    ap.add_argument("--mode", default="sync", choices=["async", "sync"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
-    ap.add_argument("--no-static", action="store_true")
+    ap.add_argument("--graphs", type=int, default=None,
+                    help="graph count for batched1024 / serving")
+    ap.add_argument("--requests", type=int, default=None,
+                    help="update batches in the serving stream")
     ap.add_argument("--param", action="append", default=[],
                     help="library parameter override name=value")
     return ap.parse_args()
 
 
+def overrides(args):
+    out = {}
+    for kv in args.param:
+        k, v = kv.split("=")
+        out[k] = float(v) if k in ("alpha", "tol", "frontier_tol") else int(v)
+    return out
+
+
 def load_workload(name):
     from paper_2407_19562_amd import inputs
-    if name == "rmat22":
+    if name in ("rmat22", "sweep"):
         n, s, d = inputs.cached("rmat_large", inputs.rmat_large)
         desc = "R-MAT 2^22 vertices, 67,108,864 edges (a=.57,b=c=.19), seed 2"
     elif name == "rmat14":
@@ -65,21 +81,27 @@ def load_workload(name):
         desc = "R-MAT 2^14 vertices, 131,072 edges (a=.57,b=c=.19), seed 1"
     else:
         n, s, d = inputs.cached("road_grid", inputs.road_grid)
-        desc = "4096x4096 road-like grid, 5% pairs removed, 1e-4 long-range, seed 3"
+        desc = ("4096x4096 bidirectional grid, 5% of pairs removed, 1e-4|E| "
+                "long-range edges, seed 3 (%d edges)" % s.size)
     return n, s, d, desc
 
 
 def batch_seed(name, frac):
-    base = {"rmat22": 2000, "rmat14": 1000, "grid4096": 3000}[name]
+    base = {"rmat22": 2000, "sweep": 2000, "rmat14": 1000, "grid4096": 3000}[name]
     fi = FRACS.index(frac) if frac in FRACS else 9
     return base + 10 * fi
 
 
-def traffic_record(kernel_tag):
-    """HBM bytes per dispatch from the committed rocprofv3 counter summary,
-    if it was taken on the current kernel source; else None."""
-    import hashlib
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel_tag}.txt")
+def kernel_sha():
+    src = os.path.join(ROOT, "paper_2407_19562_amd", "csrc", "dfpr_rank.hip")
+    return hashlib.sha1(open(src, "rb").read()).hexdigest()[:12]
+
+
+def traffic_record(tag):
+    """HBM bytes per dispatch of the rank kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel
+    source; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{tag}.txt")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -87,9 +109,7 @@ def traffic_record(kernel_tag):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    src = os.path.join(ROOT, "paper_2407_19562_amd", "csrc", "dfpr_rank.hip")
-    sha = hashlib.sha1(open(src, "rb").read()).hexdigest()[:12]
-    if kv.get("kernel_source_sha1") != sha:
+    if kv.get("kernel_source_sha1") != kernel_sha():
         return None
     try:
         return float(kv["hbm_bytes_per_dispatch"])
@@ -100,7 +120,6 @@ def traffic_record(kernel_tag):
 def cpu_baseline(n, s, d, seconds, desc):
     import oracle
     threads = os.cpu_count() or 1
-    # calibrate with one sweep, then run a bounded sample
     m, t1, _ = oracle.timed_sweeps(n, s, d, 1, threads=threads)
     sweeps = max(1, int(seconds / max(t1, 1e-3)))
     m, t, tb = oracle.timed_sweeps(n, s, d, sweeps, threads=threads)
@@ -109,6 +128,253 @@ def cpu_baseline(n, s, d, seconds, desc):
             "sample": f"{sweeps} fp64 Jacobi sweeps of Eq. 1 (static oracle) over "
                       f"{desc} plus self-loops ({m} edges/sweep), {t:.1f} s, "
                       f"CSR build ({tb:.1f} s) excluded"}
+
+
+def copy_peak_gbs(torch, dfpr):
+    nbytes = 1 << 30
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    dfpr.dfpr_stream_copy(b, a, nbytes)
+    ms = min(dfpr.dfpr_stream_copy(b, a, nbytes) for _ in range(3))
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def run_steps(g, dev_batches, warmup, steps, torch):
+    """Applies warmup + steps batches (device arrays) with one update each;
+    returns per-step records of the timed steps and the wall time."""
+    def step(b):
+        g.apply_batch(*b)
+        rc, st = g.update()
+        if rc < 0:
+            raise RuntimeError(f"update failed {rc}")
+        by, nl = g.kernel_bytes()
+        return st, by, max(nl, 1)
+
+    for i in range(warmup):
+        step(dev_batches[i])
+    torch.cuda.synchronize()
+    rec = []
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ts = time.perf_counter()
+        st, by, nl = step(dev_batches[warmup + i])
+        rec.append({"lat_ms": (time.perf_counter() - ts) * 1e3, "st": st,
+                    "bytes": by, "launches": nl})
+    torch.cuda.synchronize()
+    return rec, time.perf_counter() - t0
+
+
+def summarize(rec):
+    lat = [r["lat_ms"] for r in rec]
+    return {
+        "latency_ms": {"p50": float(np.percentile(lat, 50)),
+                       "p99": float(np.percentile(lat, 99)),
+                       "mean": statistics.mean(lat)},
+        "update_device_ms_mean": statistics.mean(r["st"].ms for r in rec),
+        "sweeps_mean": statistics.mean(r["st"].sweeps for r in rec),
+        "affected_mean": statistics.mean(r["st"].affected for r in rec),
+        "edges_gathered_mean": statistics.mean(r["st"].edges_gathered for r in rec),
+    }
+
+
+def device_batches(torch, batches):
+    return [tuple(torch.from_numpy(a).cuda() for a in
+                  (b.del_src, b.del_dst, b.ins_src, b.ins_dst)) for b in batches]
+
+
+# --- workloads ------------------------------------------------------------------
+
+def headline(args, torch, dfpr, inputs):
+    t0 = time.time()
+    n, s, d, desc = load_workload(args.workload)
+    log(f"workload {desc}: loaded in {time.time() - t0:.1f}s")
+    nb = args.warmup + args.steps
+    batches = inputs.batches(n, s, d, nb, seed=batch_seed(args.workload, args.frac),
+                             frac=args.frac)
+    dev = device_batches(torch, batches)
+    ov = overrides(args)
+    ds, dd = torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda()
+    results = {}
+    for mode in ([args.mode] + [m for m in MODES if m != args.mode]):
+        g = dfpr.Graph(n, ds, dd, precision=args.precision, mode=MODES[mode],
+                       renormalize=int(args.precision == 32), **ov)
+        rc, st = g.static()
+        static_ms, static_iters = st.ms, st.sweeps
+        log(f"[{mode}] static: iters={st.sweeps} ms={st.ms:.2f}; "
+            f"graph {dfpr.dfpr_graph_bytes(g.h) / 2**30:.2f} GiB")
+        rec, total_s = run_steps(g, dev, args.warmup, args.steps, torch)
+        g.close()
+        log(f"[{mode}] latency ms {[round(r['lat_ms'], 2) for r in rec]} "
+            f"sweeps {[r['st'].sweeps for r in rec]}")
+        results[mode] = (rec, total_s, static_ms, static_iters)
+
+    rec, total_s, static_ms, static_iters = results[args.mode]
+    kern_ms = sum(r["st"].ms_kernel for r in rec) / sum(r["launches"] for r in rec)
+    bytes_launch = sum(r["bytes"] for r in rec) / sum(r["launches"] for r in rec)
+    achieved = bytes_launch / (kern_ms * 1e-3) / 1e9
+    tag = f"df_{args.mode}_{args.workload}_fp{args.precision}"
+    kname = "k_df_async" if args.mode == "async" else "k_sync_iter"
+    summ = summarize(rec)
+    other = [m for m in MODES if m != args.mode][0]
+    orec = results[other][0]
+    result = {
+        "metric": METRIC,
+        "value": sum(r["st"].edges_gathered for r in rec) / total_s,
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": total_s * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == 64 else "f32",
+        "data": "synthetic",
+        "config": {"workload": desc,
+                   "batch": f"{args.frac:g}*|E| per step, 80% insertions / 20% "
+                            "deletions, applied in sequence",
+                   "update": f"dynamic frontier, {args.mode} "
+                             f"({'Algorithm 1, barrier per iteration' if args.mode == 'sync' else 'Algorithm 2 scheme, one persistent launch'}), "
+                             "tol 1e-10, frontier tol 1e-13, alpha 0.85"},
+        "update_latency_ms": summ["latency_ms"],
+        "update_device_ms_mean": summ["update_device_ms_mean"],
+        "apply_ms_mean": summ["latency_ms"]["mean"] - summ["update_device_ms_mean"],
+        "edges_gathered_per_step": summ["edges_gathered_mean"],
+        "sweeps_per_step": summ["sweeps_mean"],
+        "affected_per_step": summ["affected_mean"],
+        "static_recompute_ms": static_ms,
+        "static_iters": static_iters,
+        other: {"update_latency_ms_mean": summarize(orec)["latency_ms"]["mean"],
+                "sweeps_per_step": summarize(orec)["sweeps_mean"],
+                "edges_gathered_per_step": summarize(orec)["edges_gathered_mean"]},
+        "copy_peak_gbs": copy_peak_gbs(torch, dfpr),
+        "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved,
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS,
+                     "traffic": traffic_record(tag),
+                     "bytes_per_launch": bytes_launch,
+                     "launch_ms": kern_ms},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline ...")
+        result["cpu_baseline"] = cpu_baseline(n, s, d, args.cpu_seconds, desc)
+    return result
+
+
+def sweep(args, torch, dfpr, inputs):
+    n, s, d, desc = load_workload("sweep")
+    ds, dd = torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda()
+    ov = overrides(args)
+    out = {}
+    for prec in (64, 32):
+        for f in FRACS:
+            bs = inputs.batches(n, s, d, 5, seed=batch_seed("sweep", f), frac=f)
+            dev = device_batches(torch, bs)
+            g = dfpr.Graph(n, ds, dd, precision=prec, mode=MODES[args.mode],
+                           renormalize=int(prec == 32), **ov)
+            g.static()
+            upd, stat, sw = [], [], []
+            for b in dev:
+                ts = time.perf_counter()
+                g.apply_batch(*b)
+                rc, st = g.update()
+                upd.append((time.perf_counter() - ts) * 1e3)
+                sw.append(st.sweeps)
+                # static recompute of the same updated graph, for comparison
+                R = torch.empty(n, dtype=torch.float64, device="cuda")
+                g.ranks(R)
+                rc2, st2 = g.static()
+                stat.append(st2.ms)
+                g.set_ranks(R)
+            g.close()
+            out[f"fp{prec}_f{f:g}"] = {"batch_edges": bs[0].size,
+                                       "df_ms_mean": statistics.mean(upd),
+                                       "static_ms_mean": statistics.mean(stat),
+                                       "speedup_vs_static": statistics.mean(stat) / statistics.mean(upd),
+                                       "sweeps_mean": statistics.mean(sw)}
+            log(f"fp{prec} f={f:g}: {out[f'fp{prec}_f{f:g}']}")
+    return {"metric": METRIC, "workload": "sweep", "config": {"workload": desc,
+            "update": args.mode, "batches_per_size": 5}, "unit": "ms",
+            "results": out}
+
+
+def grid(args, torch, dfpr, inputs):
+    n, s, d, desc = load_workload("grid4096")
+    bs = inputs.batches(n, s, d, 5, seed=3000, frac=1e-4)
+    dev = device_batches(torch, bs)
+    ds, dd = torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda()
+    ov = overrides(args)
+    out = {}
+    for prec in (64, 32):
+        for mode in ("async", "sync"):
+            g = dfpr.Graph(n, ds, dd, precision=prec, mode=MODES[mode],
+                           renormalize=int(prec == 32), **ov)
+            rc, st = g.static()
+            rec, total_s = run_steps(g, dev, 0, len(dev), torch)
+            g.close()
+            sm = summarize(rec)
+            out[f"{mode}_fp{prec}"] = {"update_ms_mean": sm["latency_ms"]["mean"],
+                                      "sweeps_mean": sm["sweeps_mean"],
+                                      "affected_mean": sm["affected_mean"],
+                                      "edges_gathered_mean": sm["edges_gathered_mean"],
+                                      "static_ms": st.ms}
+            log(f"{mode} fp{prec}: {out[f'{mode}_fp{prec}']}")
+    return {"metric": METRIC, "workload": "grid4096", "unit": "ms",
+            "config": {"workload": desc, "batch": "1e-4*|E| (80/20), 5 in sequence"},
+            "results": out}
+
+
+def batched(args, torch, dfpr, inputs):
+    count = args.graphs or 1024
+    t0 = time.time()
+    gl = list(inputs.graph_mix(count, 5000))
+    log(f"{count} graphs generated in {time.time() - t0:.1f}s, "
+        f"{sum(x[2].size for x in gl)} edges")
+    ov = overrides(args)
+    out = {}
+    for prec in (64, 32):
+        sets = []
+        for _ in range(2):   # one set updated in one launch, one set one by one
+            hs = []
+            for g_i, (kind, n, s, d) in enumerate(gl):
+                g = dfpr.Graph(n, s, d, precision=prec, mode=0,
+                               renormalize=int(prec == 32), **ov)
+                g.static()
+                hs.append(g)
+            sets.append(hs)
+        for g_i, (kind, n, s, d) in enumerate(gl):
+            b = inputs.batches(n, s, d, 1, seed=5000 + g_i, frac=0.01)[0]
+            for hs in sets:
+                hs[g_i].apply(b)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rc, stats = dfpr.dfpr_update_many([g.h for g in sets[0]])
+        t_batched = (time.perf_counter() - t) * 1e3
+        t = time.perf_counter()
+        for g in sets[1]:
+            g.update()
+        t_seq = (time.perf_counter() - t) * 1e3
+        edges = sum(st.edges_gathered for st in stats)
+        diff = max(float(np.abs(a.ranks() - b.ranks()).max()) for a, b in zip(*sets))
+        out[f"fp{prec}"] = {"batched_ms": t_batched, "sequential_ms": t_seq,
+                            "speedup": t_seq / t_batched,
+                            "edges_gathered": edges,
+                            "edges_per_s_batched": edges / (t_batched * 1e-3),
+                            "max_abs_diff_batched_vs_alone": diff}
+        log(f"fp{prec}: {out[f'fp{prec}']}")
+        for hs in sets:
+            for g in hs:
+                g.close()
+    return {"metric": METRIC, "workload": "batched1024", "unit": "ms",
+            "config": {"workload": f"{count} graphs, edges log-uniform 1e3..1e6, "
+                       "half R-MAT half G(n,m), avg degree log-uniform 4..32, "
+                       "seeds 5001+g", "batch": "1% of each graph (80/20)"},
+            "results": out}
+
+
+def serving(args, torch, dfpr, inputs):
+    from paper_2407_19562_amd import serving as srv
+    return srv.bench(args, torch, dfpr, inputs, log)
 
 
 def main():
@@ -122,115 +388,9 @@ def main():
     from paper_2407_19562_amd import dfpr, inputs
     assert torch.cuda.is_available(), "no HIP device"
     torch.cuda.set_device(0)
-
-    t0 = time.time()
-    n, s, d, desc = load_workload(args.workload)
-    log(f"workload {desc}: generated in {time.time() - t0:.1f}s")
-    nb = args.warmup + args.steps
-    batches = inputs.batches(n, s, d, nb, seed=batch_seed(args.workload, args.frac),
-                             frac=args.frac)
-    dev = [tuple(torch.from_numpy(a).cuda() for a in
-                 (b.del_src, b.del_dst, b.ins_src, b.ins_dst)) for b in batches]
-    overrides = {}
-    for kv in args.param:
-        k, v = kv.split("=")
-        overrides[k] = float(v) if k in ("alpha", "tol", "frontier_tol") else int(v)
-    mode = dfpr.DFPR_ASYNC if args.mode == "async" else dfpr.DFPR_SYNC
-    stream = torch.cuda.current_stream()
-    g = dfpr.Graph(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda(),
-                   precision=args.precision, mode=mode,
-                   renormalize=int(args.precision == 32), **overrides)
-    log(f"graph on device: {dfpr.dfpr_graph_bytes(g.h) / 2**30:.2f} GiB")
-    rc, st = g.static()
-    static_ms = st.ms
-    static_sweeps = st.sweeps
-    log(f"static: rc={rc} iters={st.sweeps} ms={st.ms:.2f}")
-
-    def step(b):
-        ad, ai = g.apply_batch(*b)
-        rc, st = g.update()
-        if rc < 0:
-            raise RuntimeError(f"update failed {rc}")
-        return ad, ai, st
-
-    for i in range(args.warmup):
-        step(dev[i])
-    torch.cuda.synchronize()
-    lat, upd, kern, edges, byts, sweeps, aff, launches = [], [], [], [], [], [], [], []
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for i in range(args.steps):
-        ts = time.perf_counter()
-        ad, ai, st = step(dev[args.warmup + i])
-        lat.append((time.perf_counter() - ts) * 1e3)
-        b, nl = g.kernel_bytes()
-        upd.append(st.ms)
-        kern.append(st.ms_kernel)
-        edges.append(st.edges_gathered)
-        byts.append(b)
-        launches.append(max(nl, 1))
-        sweeps.append(st.sweeps)
-        aff.append(st.affected)
-    torch.cuda.synchronize()
-    total_s = time.perf_counter() - t_start
-    log(f"steps: latency ms {[round(x, 2) for x in lat]} sweeps {sweeps} affected {aff}")
-
-    # stream-copy calibration of the achievable HBM bandwidth
-    nbytes = 1 << 30
-    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-    bb = torch.empty_like(a)
-    dfpr.dfpr_stream_copy(bb, a, nbytes)
-    cms = min(dfpr.dfpr_stream_copy(bb, a, nbytes) for _ in range(3))
-    copy_gbs = 2 * nbytes / (cms * 1e-3) / 1e9
-    del a, bb
-
-    # per launch of the rank kernel (one per update when async, one per
-    # iteration when synchronous)
-    kern_avg_ms = sum(kern) / sum(launches)
-    bytes_avg = sum(byts) / sum(launches)
-    achieved = bytes_avg / (kern_avg_ms * 1e-3) / 1e9
-    tag = f"df_{args.mode}_{args.workload}_fp{args.precision}"
-    hbm = traffic_record(tag)
-    kname = "k_df_async" if args.mode == "async" else "k_sync_iter"
-    result = {
-        "metric": METRIC,
-        "value": sum(edges) / total_s,
-        "unit": "edges/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": total_s * 1e3 / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if args.precision == 64 else "f32",
-        "data": "synthetic",
-        "config": {"workload": desc, "batch": f"{args.frac:g}*|E| per step, 80% "
-                   "insertions / 20% deletions, applied in sequence",
-                   "update": f"dynamic frontier, {args.mode}, tol 1e-10, "
-                   "frontier tol 1e-13, alpha 0.85"},
-        "update_latency_ms": {"p50": float(np.percentile(lat, 50)),
-                              "p99": float(np.percentile(lat, 99)),
-                              "mean": statistics.mean(lat)},
-        "update_device_ms_mean": statistics.mean(upd),
-        "apply_ms_mean": statistics.mean(lat) - statistics.mean(upd),
-        "edges_gathered_per_step": statistics.mean(edges),
-        "sweeps_per_step": statistics.mean(sweeps),
-        "affected_per_step": statistics.mean(aff),
-        "static_recompute_ms": None if args.no_static else static_ms,
-        "static_iters": static_sweeps,
-        "copy_peak_gbs": copy_gbs,
-        "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved,
-                     "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS,
-                     "traffic": hbm,
-                     "bytes_per_launch": bytes_avg,
-                     "launch_ms": kern_avg_ms},
-    }
-    g.close()
-    if not args.no_cpu_baseline:
-        log("cpu baseline ...")
-        result["cpu_baseline"] = cpu_baseline(n, s, d, args.cpu_seconds, desc)
+    fn = {"rmat22": headline, "rmat14": headline, "sweep": sweep,
+          "grid4096": grid, "batched1024": batched, "serving": serving}[args.workload]
+    result = fn(args, torch, dfpr, inputs)
     print(json.dumps(result), flush=True)
 
 

@@ -1,0 +1,210 @@
+"""Serving many resident graphs: update batches arrive as a stream and are
+applied with continuous batching.
+
+Every graph keeps its slack CSR and ranks resident on the device.  Requests
+(one update batch for one graph) queue per graph in arrival order.  The
+loop runs in rounds: each round admits the requests that have arrived (as
+long as free device memory covers their staging), applies every admitted
+graph's queued batches in FIFO order (at most `coalesce` per graph; batches
+applied before one update accumulate their marks, which is the same as
+applying their union), and then updates all those graphs together in one
+persistent launch (dfpr_update_many).  A request completes when the round
+that applied it finishes; its latency runs from arrival to that moment.
+Requests arriving during a round join the next one.
+"""
+from __future__ import annotations
+
+import collections
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import dfpr, inputs
+
+
+@dataclass
+class Request:
+    graph: int
+    batch: inputs.Batch
+    arrival: float            # seconds from the start of the run
+    done: float = math.nan    # completion time
+    round: int = -1
+
+
+@dataclass
+class Report:
+    latencies_ms: list = field(default_factory=list)
+    rounds: int = 0
+    updates: int = 0
+    wall_s: float = 0.0
+    edges_gathered: int = 0
+    batch_edges: int = 0
+    admission_waits: int = 0
+
+    def summary(self):
+        lat = np.array(self.latencies_ms) if self.latencies_ms else np.zeros(1)
+        return {"requests": len(self.latencies_ms),
+                "p50_ms": float(np.percentile(lat, 50)),
+                "p99_ms": float(np.percentile(lat, 99)),
+                "mean_ms": float(lat.mean()),
+                "throughput_batches_per_s": len(self.latencies_ms) / max(self.wall_s, 1e-9),
+                "throughput_batch_edges_per_s": self.batch_edges / max(self.wall_s, 1e-9),
+                "edges_gathered_per_s": self.edges_gathered / max(self.wall_s, 1e-9),
+                "rounds": self.rounds, "updates": self.updates,
+                "admission_waits": self.admission_waits,
+                "wall_s": self.wall_s}
+
+
+class Server:
+    """Resident graphs plus the continuous-batching loop."""
+
+    def __init__(self, graphs, precision: int = 32, coalesce: int = 16,
+                 reserve_bytes: int = 1 << 30, **params):
+        self.graphs = []
+        for n, s, d in graphs:
+            g = dfpr.Graph(n, s, d, precision=precision, mode=dfpr.DFPR_ASYNC,
+                           renormalize=int(precision == 32), **params)
+            g.static()
+            self.graphs.append(g)
+        self.coalesce = coalesce
+        self.reserve = reserve_bytes
+
+    def close(self):
+        for g in self.graphs:
+            g.close()
+
+    def _free_bytes(self):
+        try:
+            import torch
+            return torch.cuda.mem_get_info()[0]
+        except Exception:
+            return 1 << 62
+
+    def run(self, requests, open_loop: bool = True) -> Report:
+        """Serves `requests` (sorted by arrival).  open_loop: requests are
+        released at their arrival times; otherwise all are available at 0."""
+        rep = Report()
+        queues = [collections.deque() for _ in self.graphs]
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        t0 = time.perf_counter()
+        done = 0
+        while done < len(requests):
+            now = time.perf_counter() - t0
+            # admission: arrived requests whose staging fits in free memory
+            free = None
+            while pending and (not open_loop or pending[0].arrival <= now):
+                r = pending[0]
+                need = 48 * r.batch.size + self.reserve
+                if free is None:
+                    free = self._free_bytes()
+                if need > free:
+                    rep.admission_waits += 1
+                    break
+                free -= 48 * r.batch.size
+                queues[r.graph].append(pending.popleft())
+            active = [i for i, q in enumerate(queues) if q]
+            if not active:
+                if pending:
+                    wait = pending[0].arrival - (time.perf_counter() - t0)
+                    if wait > 0:
+                        time.sleep(min(wait, 0.05))
+                continue
+            served = []
+            for i in active:
+                for _ in range(min(self.coalesce, len(queues[i]))):
+                    r = queues[i].popleft()
+                    self.graphs[i].apply(r.batch)
+                    rep.batch_edges += r.batch.size
+                    served.append(r)
+            rc, stats = dfpr.dfpr_update_many([self.graphs[i].h for i in active])
+            if rc < 0:
+                raise dfpr.DfprError(rc, "dfpr_update_many")
+            end = time.perf_counter() - t0
+            rep.rounds += 1
+            rep.updates += len(active)
+            rep.edges_gathered += sum(st.edges_gathered for st in stats)
+            for r in served:
+                r.done = end
+                r.round = rep.rounds
+                rep.latencies_ms.append((end - r.arrival) * 1e3)
+            done += len(served)
+        rep.wall_s = time.perf_counter() - t0
+        return rep
+
+
+def make_stream(graph_sizes, count: int, seed: int, rate: float | None,
+                lo: float = 1, hi: float = 1e5, ins_share: float = 0.8,
+                edges_of=None):
+    """Poisson stream: `count` requests, target graph uniform, size
+    log-uniform in [lo, hi] edges (capped at 1% of the graph), arrivals
+    with mean rate `rate` per second (None: all at t = 0).  `edges_of(g)`
+    returns (n, src, dst) of graph g for drawing its batches."""
+    rng = np.random.default_rng(seed)
+    gids = rng.integers(0, len(graph_sizes), count)
+    sizes = np.exp(rng.uniform(math.log(lo), math.log(hi), count))
+    arrivals = (np.cumsum(rng.exponential(1.0 / rate, count)) if rate
+                else np.zeros(count))
+    per_graph = collections.defaultdict(list)
+    for k in range(count):
+        cap = max(1, graph_sizes[gids[k]] // 100)
+        per_graph[int(gids[k])].append((k, int(min(cap, max(1, round(sizes[k]))))))
+    reqs = [None] * count
+    for gidx, items in per_graph.items():
+        n, s, d = edges_of(gidx)
+        total = sum(sz for _, sz in items)
+        # draw the graph's batches together so they stay true changes when
+        # applied in sequence (distinct deletions, distinct non-edges)
+        pool = inputs.batches(n, s, d, 1, seed=seed * 1000 + gidx, size=total,
+                              ins_share=ins_share)[0]
+        di = ii = 0
+        for k, sz in items:
+            nd = sz - int(round(ins_share * sz))
+            ni = sz - nd
+            b = inputs.Batch(pool.del_src[di:di + nd], pool.del_dst[di:di + nd],
+                             pool.ins_src[ii:ii + ni], pool.ins_dst[ii:ii + ni])
+            di += nd
+            ii += ni
+            reqs[k] = Request(int(gids[k]), b, float(arrivals[k]))
+    return reqs
+
+
+def bench(args, torch, dfpr_mod, inputs_mod, log):
+    """Serving benchmark: resident R-MAT graphs, closed-loop saturated
+    throughput X, then open-loop Poisson streams at 0.5 X and 0.8 X."""
+    count = args.graphs or 64
+    nreq = args.requests or 5000
+    t0 = time.time()
+    graphs = list(inputs.resident_mix(count, 4000))
+    log(f"{count} resident graphs generated in {time.time() - t0:.1f}s, "
+        f"{sum(s.size for _, s, _ in graphs)} edges")
+    sizes = [s.size for _, s, _ in graphs]
+    srv = Server(graphs, precision=32)
+    try:
+        res = {}
+        closed = make_stream(sizes, nreq, 4, None, edges_of=lambda g: graphs[g])
+        rep = srv.run(closed, open_loop=False)
+        X = rep.summary()["throughput_batches_per_s"]
+        res["closed_loop"] = rep.summary()
+        log(f"closed loop: {res['closed_loop']}")
+        for frac in (0.5, 0.8):
+            reqs = make_stream(sizes, nreq, 40 + int(frac * 10), frac * X,
+                               edges_of=lambda g: graphs[g])
+            rep = srv.run(reqs, open_loop=True)
+            res[f"open_loop_{frac}X"] = rep.summary()
+            log(f"open loop {frac}X: {res[f'open_loop_{frac}X']}")
+    finally:
+        srv.close()
+    o = res["open_loop_0.8X"]
+    return {"metric": "p50/p99 served latency (update latency ms/batch)",
+            "workload": "serving",
+            "value": o["throughput_batches_per_s"], "unit": "batches/s",
+            "p50_ms": o["p50_ms"], "p99_ms": o["p99_ms"],
+            "config": {"graphs": f"{count} R-MAT graphs, n log-uniform 2^16..2^21, "
+                       "avg degree log-uniform 8..32, seeds 4001+g",
+                       "stream": f"{nreq} batches, sizes log-uniform 1..1e5 edges "
+                       "(at most 1% of the graph), 80/20, target uniform",
+                       "ranks": "fp32 storage and sums, fp64 change tests and "
+                       "renormalisation", "coalesce": srv.coalesce},
+            "results": res}
