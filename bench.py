@@ -81,7 +81,7 @@ def load_workload(name):
         desc = "R-MAT 2^14 vertices, 131,072 edges (a=.57,b=c=.19), seed 1"
     else:
         n, s, d = inputs.cached("road_grid", inputs.road_grid)
-        desc = ("4096x4096 bidirectional grid, 5% of pairs removed, 1e-4|E| "
+        desc = ("4096x4096 bidirectional grid, 5%% of pairs removed, 1e-4|E| "
                 "long-range edges, seed 3 (%d edges)" % s.size)
     return n, s, d, desc
 
@@ -273,13 +273,14 @@ def sweep(args, torch, dfpr, inputs):
             g = dfpr.Graph(n, ds, dd, precision=prec, mode=MODES[args.mode],
                            renormalize=int(prec == 32), **ov)
             g.static()
-            upd, stat, sw = [], [], []
+            upd, stat, sw, aff = [], [], [], []
             for b in dev:
                 ts = time.perf_counter()
                 g.apply_batch(*b)
                 rc, st = g.update()
                 upd.append((time.perf_counter() - ts) * 1e3)
                 sw.append(st.sweeps)
+                aff.append(st.affected)
                 # static recompute of the same updated graph, for comparison
                 R = torch.empty(n, dtype=torch.float64, device="cuda")
                 g.ranks(R)
@@ -288,6 +289,7 @@ def sweep(args, torch, dfpr, inputs):
                 g.set_ranks(R)
             g.close()
             out[f"fp{prec}_f{f:g}"] = {"batch_edges": bs[0].size,
+                                       "affected_mean": statistics.mean(aff),
                                        "df_ms_mean": statistics.mean(upd),
                                        "static_ms_mean": statistics.mean(stat),
                                        "speedup_vs_static": statistics.mean(stat) / statistics.mean(upd),

@@ -90,14 +90,13 @@ typedef struct {
                             in the lock-free scheme                         */
   int32_t block_size;    /* threads per workgroup (64, 128, 192 or 256)     */
   int32_t reorder;       /* internal vertex order, fixed at creation:
-                            0 (default) keep the caller's ids, 1 sort by
-                            decreasing out-degree (hot contributions share
-                            cache lines), 2 sort only when the out-degree is
-                            skewed (max >= 8 x mean).  Ids at the ABI are
-                            always the caller's.  Sorting clusters hub rows
-                            into the same 256-vertex steps; without row
-                            splitting that unbalances the gathers, so it is
-                            off by default.                                */
+                            0 keep the caller's ids; 1 sort by decreasing
+                            out-degree, so the contributions read most often
+                            share cache lines; 2 (default) sort when the
+                            graph is large (n >= 2^20), its out-degree
+                            skewed (max >= 8 x mean) and the mode at
+                            creation is DFPR_SYNC.  Ids at the ABI are
+                            always the caller's.                           */
   int32_t renormalize;   /* fp32: rescale ranks to sum 1 (fp64 sum) after
                             each update                                     */
   int32_t timeout_ms;    /* watchdog for the persistent kernel (0: none)    */

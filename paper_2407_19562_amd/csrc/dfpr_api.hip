@@ -78,7 +78,7 @@ static void release(dfpr_graph *g) {
                   g->R[0],    g->R[1],    g->C[0],    g->C[1],
                   g->flags,   g->wl,      g->ctl,     g->sync_max,
                   g->sync_grab, g->sync_len, g->gflags, g->gwl,
-                  g->ext2int, g->int2ext};
+                  g->ext2int, g->int2ext, g->steps, g->epre};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (auto &s : g->scratch)
@@ -104,6 +104,8 @@ static int alloc_graph(dfpr_graph *g) {
   const size_t fbytes = (n + 3) / 4 * 4;
   DFPR_HIP(hipMalloc(&g->flags, fbytes));
   DFPR_HIP(hipMemsetAsync(g->flags, 0, fbytes, g->stream));
+  DFPR_HIP(hipMalloc(&g->steps, (n + 1) * 4));
+  DFPR_HIP(hipMalloc(&g->epre, n * 8));
   DFPR_HIP(hipMalloc(&g->wl, n * 4));
   DFPR_HIP(hipMemsetAsync(g->wl, 0xFF, n * 4, g->stream));
   g->ngroups = (int32_t)((n + kGroup - 1) / kGroup);
@@ -162,7 +164,7 @@ int dfpr_params_default(dfpr_params *p) {
   p->wave_min_degree = 32;
   p->chunk = 256;
   p->block_size = 256;
-  p->reorder = 0;
+  p->reorder = 2;
   p->renormalize = 0;
   p->timeout_ms = 60000;
   p->grid_blocks = 0;

@@ -163,7 +163,12 @@ int build_graph(dfpr_graph *g, int64_t m, const int32_t *src,
     int32_t maxdeg = 0;
     for (int32_t x : hc) maxdeg = x > maxdeg ? x : maxdeg;
     const double mean = (double)m / (double)n;
-    if (g->p.reorder == 1 || (double)maxdeg >= 8.0 * mean) {
+    // automatic: large, skewed graphs under the barrier-based scheme (its
+    // edge-balanced steps spread the clustered hub rows; the lock-free
+    // scheme's 256-vertex groups would not)
+    const bool autosort = (double)maxdeg >= 8.0 * mean && n >= (1 << 20) &&
+                          g->p.mode == DFPR_SYNC;
+    if (g->p.reorder == 1 || (g->p.reorder == 2 && autosort)) {
       if ((rc = scratch_get(g, 0, (size_t)n * 8, &keys_a))) return rc;
       if ((rc = scratch_get(g, 1, (size_t)n * 8, &keys_b))) return rc;
       k_order_keys<<<grid_for(n, cu), 256, 0, s>>>(n, cnt, maxdeg,

@@ -57,6 +57,7 @@ constexpr uint64_t kInflightMask = 0xFFFFull;
 struct Ctl {
   alignas(128) unsigned long long state;  // async scheduling word
   alignas(128) unsigned long long tail;   // vertex worklist length
+  unsigned long long nsteps;              // steps of the current worklist
   alignas(128) unsigned long long gtail;  // group worklist length
   alignas(128) long long change_sweep;    // last sweep in which a claim saw a
                                           // change above the frontier tol
@@ -113,6 +114,8 @@ struct dfpr_graph {
   int32_t ngroups = 0;
   uint32_t *gflags = nullptr;  // [ngroups] bytes
   int32_t *gwl = nullptr;      // group worklist [ngroups], unused slots -1
+  int32_t *steps = nullptr;    // step starts over the worklist [n + 1]
+  int64_t *epre = nullptr;     // edge prefix over the worklist [n]
   int32_t *ext2int = nullptr;  // caller id -> internal id (null: identity)
   int32_t *int2ext = nullptr;  // internal id -> caller id
   dfpr::Ctl *ctl = nullptr;

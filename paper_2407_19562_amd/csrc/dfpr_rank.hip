@@ -34,8 +34,10 @@
 #include <cstring>
 #include <vector>
 
+#include <rocprim/device/device_scan.hpp>
 #include <rocprim/device/device_select.hpp>
 #include <rocprim/iterator/counting_iterator.hpp>
+#include <rocprim/iterator/transform_iterator.hpp>
 
 #include "dfpr_common.h"
 
@@ -547,34 +549,34 @@ __global__ void __launch_bounds__(256) k_df_async_many(const RankArgs<T> *descs,
   flush_graph<T>(A.ctl, cnt, newly);
 }
 
+// One iteration of the barrier-based scheme (or of static PageRank): the
+// worklist (all vertices for static) is cut into steps of at most 256
+// entries and about kStepEdges in-edges, and wavefronts claim steps.
 template <typename T, int MODE>
-__global__ void __launch_bounds__(256) k_sync_iter(RankArgs<T> A, int iter) {
+__global__ void __launch_bounds__(256) k_sync_iter(RankArgs<T> A, int iter,
+                                                   const int32_t *steps) {
   if (A.ctl->sync_done) return;
   __shared__ WaveLds<T> lds[256 / kWave];
   WaveLds<T> &L = lds[threadIdx.x / kWave];
   const int lane = lane_id();
   Counters cnt;
   double maxdr = 0.0;
-  const unsigned long long len =
-      MODE == kAll ? (unsigned long long)A.n : A.sync_len[iter];
-  const unsigned long long chunk = (unsigned long long)A.chunk;
+  const unsigned long long nsteps = A.sync_len[iter];
   while (true) {
-    unsigned long long p = 0;
-    if (lane == 0) p = atomicAdd(&A.sync_grab[iter], chunk);
-    p = bcast0(p);
-    if (p >= len) break;
-    const unsigned long long end = p + chunk < len ? p + chunk : len;
-    for (unsigned long long g0 = p; g0 < end; g0 += kRows) {
-      int32_t vv[kQ];
+    unsigned long long u = 0;
+    if (lane == 0) u = atomicAdd(&A.sync_grab[iter], 1ull);
+    u = bcast0(u);
+    if (u >= nsteps) break;
+    const int32_t start = steps[u], end = steps[u + 1];
+    int32_t vv[kQ];
 #pragma unroll
-      for (int k = 0; k < kQ; ++k) {
-        const unsigned long long pos = g0 + k * kWave + lane;
-        vv[k] = pos < end ? (MODE == kAll ? (int32_t)pos : A.wl[pos]) : -1;
-      }
-      bool unused_moved = false;
-      long long unused_newly = 0;
-      process_step<T, MODE>(A, L, vv, cnt, maxdr, unused_newly, unused_moved);
+    for (int k = 0; k < kQ; ++k) {
+      const int32_t pos = start + k * kWave + lane;
+      vv[k] = pos < end ? (MODE == kAll ? pos : A.wl[pos]) : -1;
     }
+    bool unused_moved = false;
+    long long unused_newly = 0;
+    process_step<T, MODE>(A, L, vv, cnt, maxdr, unused_newly, unused_moved);
   }
   maxdr = wave_max(maxdr);
   if (lane == 0 && maxdr > 0.0)
@@ -591,8 +593,8 @@ __global__ void k_sync_finish(Ctl *ctl, const unsigned long long *sync_max,
     ctl->sync_done = 1;
     ctl->sync_final = iter + 1;
     ctl->sync_conv = md <= tol ? 1 : 0;
-  } else if (df) {
-    sync_len[iter + 1] = ctl->tail;
+  } else {
+    sync_len[iter + 1] = ctl->nsteps;
   }
 }
 
@@ -606,7 +608,7 @@ __global__ void k_sync_begin(Ctl *ctl, unsigned long long *sync_max,
     sync_len[i] = 0;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    sync_len[0] = ctl->tail;
+    sync_len[0] = ctl->nsteps;
     ctl->sync_done = 0;
     ctl->sync_final = 0;
     ctl->sync_conv = 0;
@@ -906,6 +908,67 @@ int rebuild_worklist(dfpr_graph *g) {
   return DFPR_OK;
 }
 
+// in-edges a step aims at (a row is never split, so a step holding one
+// heavy row can exceed it)
+constexpr int64_t kStepEdges = 16384;
+
+struct StepLen {
+  const int32_t *list;  // worklist, or null for the identity (all vertices)
+  const int32_t *deg;
+  const unsigned long long *len;
+  __device__ int64_t operator()(int64_t i) const {
+    if ((unsigned long long)i >= *len) return 0;
+    return (int64_t)deg[list ? list[i] : (int32_t)i] + 1;
+  }
+};
+
+struct StepStart {
+  const int64_t *pre;
+  const unsigned long long *len;
+  __device__ uint8_t operator()(int64_t i) const {
+    if ((unsigned long long)i >= *len) return 0;
+    if ((i & (kRows - 1)) == 0) return 1;
+    return (pre[i] / kStepEdges) != (pre[i - 1] / kStepEdges) ? 1 : 0;
+  }
+};
+
+__global__ void k_steps_sentinel(int32_t *steps, const unsigned long long *nsteps,
+                                 const unsigned long long *len) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) steps[*nsteps] = (int32_t)*len;
+}
+
+__global__ void k_set_len(unsigned long long *dst, unsigned long long v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = v;
+}
+
+// Cuts the first *len entries of `list` (or of the identity) into steps:
+// a step starts every 256 entries and wherever the running in-edge count
+// crosses a multiple of kStepEdges.  Writes g->steps[0 .. nsteps] and
+// ctl->nsteps on the device.
+int build_steps(dfpr_graph *g, const int32_t *list, const unsigned long long *len) {
+  hipStream_t s = g->stream;
+  const size_t n = (size_t)g->n;
+  rocprim::counting_iterator<int64_t> idx(0);
+  auto lens = rocprim::make_transform_iterator(idx, StepLen{list, g->in.deg, len});
+  size_t tb = 0;
+  DFPR_HIP(rocprim::exclusive_scan(nullptr, tb, lens, g->epre, (int64_t)0, n,
+                                   rocprim::plus<int64_t>(), s));
+  void *tmp = nullptr;
+  int rc = scratch_get(g, 14, tb, &tmp);
+  if (rc) return rc;
+  DFPR_HIP(rocprim::exclusive_scan(tmp, tb, lens, g->epre, (int64_t)0, n,
+                                   rocprim::plus<int64_t>(), s));
+  auto starts = rocprim::make_transform_iterator(idx, StepStart{g->epre, len});
+  rocprim::counting_iterator<int32_t> pos(0);
+  tb = 0;
+  DFPR_HIP(rocprim::select(nullptr, tb, pos, starts, g->steps, &g->ctl->nsteps, n, s));
+  if ((rc = scratch_get(g, 14, tb, &tmp))) return rc;
+  DFPR_HIP(rocprim::select(tmp, tb, pos, starts, g->steps, &g->ctl->nsteps, n, s));
+  k_steps_sentinel<<<1, 64, 0, s>>>(g->steps, &g->ctl->nsteps, len);
+  DFPR_HIP(hipGetLastError());
+  return DFPR_OK;
+}
+
 template <typename T>
 int run_sync(dfpr_graph *g, int mode, dfpr_stats *st) {
   hipStream_t s = g->stream;
@@ -917,9 +980,17 @@ int run_sync(dfpr_graph *g, int mode, dfpr_stats *st) {
     DFPR_HIP(hipMemcpyAsync(g->C[1 - g->cur], g->C[g->cur], (size_t)g->n * g->elem,
                             hipMemcpyDeviceToDevice, s));
   }
-  if (mode != kAll) {
-    int rc = rebuild_worklist(g);
-    if (rc) return rc;
+  {
+    int rc;
+    if (mode != kAll) {
+      if ((rc = rebuild_worklist(g))) return rc;
+      if ((rc = build_steps(g, g->wl, &g->ctl->tail))) return rc;
+    } else {
+      // static: every vertex, in id order; the length lives in sync_max[0]
+      // until k_sync_begin clears it
+      k_set_len<<<1, 64, 0, s>>>(g->sync_max, (unsigned long long)g->n);
+      if ((rc = build_steps(g, nullptr, g->sync_max))) return rc;
+    }
   }
   k_sync_begin<<<4, 256, 0, s>>>(g->ctl, g->sync_max, g->sync_grab, g->sync_len, iters);
   DFPR_HIP(hipGetLastError());
@@ -930,10 +1001,11 @@ int run_sync(dfpr_graph *g, int mode, dfpr_stats *st) {
   int it = 0;
   for (; it < iters; ++it) {
     RankArgs<T> A = make_args<T>(g, (g->cur + it) & 1, (g->cur + it + 1) & 1);
-    kern<<<blocks, g->p.block_size, 0, s>>>(A, it);
+    kern<<<blocks, g->p.block_size, 0, s>>>(A, it, g->steps);
     if (mode != kAll) {
       int rc = rebuild_worklist(g);
       if (rc) return rc;
+      if ((rc = build_steps(g, g->wl, &g->ctl->tail))) return rc;
     }
     k_sync_finish<<<1, 64, 0, s>>>(g->ctl, g->sync_max, g->sync_len, it, g->p.tol,
                                    iters, mode == kSyncDF);
