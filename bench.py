@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--precision", type=int, default=64, choices=[32, 64])
     ap.add_argument("--mode", default="sync", choices=["async", "sync"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batched1024: keep the default launch parameters")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
     ap.add_argument("--graphs", type=int, default=None,
@@ -344,6 +346,18 @@ def batched(args, torch, dfpr, inputs):
                 g.static()
                 hs.append(g)
             sets.append(hs)
+        if not args.no_autotune:
+            # launch parameters from trial updates of the same graphs (their
+            # edge sets and ranks are restored afterwards)
+            from paper_2407_19562_amd import autotune
+            t0 = time.perf_counter()
+            best, table = autotune.tune(sets[0], frac=0.01, seed=777)
+            for g in sets[1]:
+                g.set_params(**best)
+            out[f"fp{prec}_autotune"] = {
+                "best": best, "seconds": time.perf_counter() - t0,
+                "trials_ms": [(round(t * 1e3, 1), c) for t, c in table]}
+            log(f"fp{prec} autotune: {best}")
         for g_i, (kind, n, s, d) in enumerate(gl):
             b = inputs.batches(n, s, d, 1, seed=5000 + g_i, frac=0.01)[0]
             for hs in sets:

@@ -81,13 +81,17 @@ typedef struct {
   int32_t precision;     /* 64: fp64 ranks; 32: fp32 ranks and sums with fp64
                             change tests and norms                          */
   int32_t mode;          /* DFPR_ASYNC or DFPR_SYNC                         */
-  int32_t kahan_min_degree; /* fp32: compensated sums for in-degree >= this */
-  int32_t wave_min_degree;  /* in-degree at or above which a whole wavefront
-                               gathers one vertex (else one lane each)      */
-  int32_t chunk;         /* vertices per dynamic grab: worklist positions in
-                            the synchronous scheme (multiple of 64), whole
-                            256-vertex groups (chunk / 256, at least one)
-                            in the lock-free scheme                         */
+  int32_t kahan_min_degree; /* fp32 ranks: rows with at least this in-degree
+                               accumulate in fp64, shorter rows in fp32    */
+  int32_t split_min_degree; /* barrier-based scheme and static PageRank:
+                               rows with at least this in-degree are summed
+                               in pieces of 4096 in-edges by whole
+                               wavefronts (partial sums added in piece
+                               order), the rest in edge-balanced steps of
+                               up to 256 rows                              */
+  int32_t chunk;         /* lock-free scheme: worklist groups per dynamic
+                            grab are chunk / 256 (at least one); a multiple
+                            of 64 in [64, 4096]                             */
   int32_t block_size;    /* threads per workgroup (64, 128, 192 or 256)     */
   int32_t reorder;       /* internal vertex order, fixed at creation:
                             0 keep the caller's ids; 1 sort by decreasing

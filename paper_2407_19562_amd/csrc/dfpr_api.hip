@@ -57,7 +57,7 @@ int check_params(const dfpr_params *p) {
   if (p->precision != 32 && p->precision != 64)
     return fail(DFPR_EINVAL, "precision must be 32 or 64");
   if (p->mode != DFPR_ASYNC && p->mode != DFPR_SYNC) return fail(DFPR_EINVAL, "bad mode");
-  if (p->wave_min_degree < 1) return fail(DFPR_EINVAL, "wave_min_degree must be >= 1");
+  if (p->split_min_degree < 1) return fail(DFPR_EINVAL, "split_min_degree must be >= 1");
   if (p->kahan_min_degree < 0) return fail(DFPR_EINVAL, "kahan_min_degree must be >= 0");
   if (p->chunk < 64 || p->chunk % 64 || p->chunk > 4096)
     return fail(DFPR_EINVAL, "chunk must be a multiple of 64 in [64, 4096]");
@@ -78,7 +78,9 @@ static void release(dfpr_graph *g) {
                   g->R[0],    g->R[1],    g->C[0],    g->C[1],
                   g->flags,   g->wl,      g->ctl,     g->sync_max,
                   g->sync_grab, g->sync_len, g->gflags, g->gwl,
-                  g->ext2int, g->int2ext, g->steps, g->epre};
+                  g->ext2int, g->int2ext, g->steps, g->epre,
+                  g->split.lrow, g->split.lpre, g->split.lcnt, g->split.prow,
+                  g->split.ppart};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (auto &s : g->scratch)
@@ -161,7 +163,7 @@ int dfpr_params_default(dfpr_params *p) {
   p->precision = 64;
   p->mode = DFPR_ASYNC;
   p->kahan_min_degree = 64;
-  p->wave_min_degree = 32;
+  p->split_min_degree = 2048;
   p->chunk = 256;
   p->block_size = 256;
   p->reorder = 2;

@@ -58,6 +58,8 @@ struct Ctl {
   alignas(128) unsigned long long state;  // async scheduling word
   alignas(128) unsigned long long tail;   // vertex worklist length
   unsigned long long nsteps;              // steps of the current worklist
+  unsigned long long nlong;               // rows gathered in pieces
+  unsigned long long npieces;             // their pieces
   alignas(128) unsigned long long gtail;  // group worklist length
   alignas(128) long long change_sweep;    // last sweep in which a claim saw a
                                           // change above the frontier tol
@@ -90,6 +92,21 @@ struct Adj {
   int64_t adj_cap = 0;  // slots allocated in adj
 };
 
+// Rows gathered in pieces (barrier-based scheme and static PageRank): a
+// worklist row whose in-degree reaches split_min_degree is cut into pieces
+// of kPiece in-edges.  Whole wavefronts sum one piece each; the wavefront
+// that finishes a row's last piece adds the partial sums in piece order and
+// completes the vertex.
+constexpr int kPiece = 4096;
+struct Split {
+  int32_t *lrow = nullptr;  // [lcap] vertex of long row j
+  int32_t *lpre = nullptr;  // [lcap + 1] first piece of long row j
+  int32_t *lcnt = nullptr;  // [lcap] pieces of row j finished (the last resets it)
+  int32_t *prow = nullptr;  // [pcap] long row of piece p
+  double *ppart = nullptr;  // [pcap] partial sum of piece p
+  int64_t lcap = 0, pcap = 0;
+};
+
 // Reusable device scratch of apply_batch (grown on demand).
 struct Scratch {
   void *p = nullptr;
@@ -116,6 +133,7 @@ struct dfpr_graph {
   int32_t *gwl = nullptr;      // group worklist [ngroups], unused slots -1
   int32_t *steps = nullptr;    // step starts over the worklist [n + 1]
   int64_t *epre = nullptr;     // edge prefix over the worklist [n]
+  dfpr::Split split;           // rows gathered in pieces
   int32_t *ext2int = nullptr;  // caller id -> internal id (null: identity)
   int32_t *int2ext = nullptr;  // internal id -> caller id
   dfpr::Ctl *ctl = nullptr;

@@ -2,34 +2,36 @@
 // convergence (Section 4; Algorithms 1 and 2), plus static / naive-dynamic
 // PageRank (Algorithm 3; Section 3.5.1) and small helpers.
 //
-// Work unit: one wavefront takes 64 vertices, one per lane: 64 worklist
-// positions (synchronous scheme, static) or a quarter of a 256-vertex id
-// group (lock-free scheme).
-//   gather: a lane sums its own in-row when the in-degree is below
-//     wave_min_degree (16-byte index loads, two accumulators); rows at or
-//     above it are gathered by the whole wavefront, one row at a time,
-//     64 lanes striding the row and a shuffle reduction.  The sum reads the
-//     contributions C[u] = R[u] / (out-degree(u) + 1), so one random 4- or
-//     8-byte load per in-edge; the implicit self-loop adds C[v].
-//   update: r = (1 - alpha)/n + alpha * sum, dr = |r - R[v]|.
-//   frontier (dr > frontier_tol): every out-neighbour gets the affected
-//     flag (and, in the lock-free scheme, the not-converged flag); newly
-//     affected vertices are appended with one atomic per wavefront.
-//   convergence: lock-free scheme -- R_C[v] = (dr > tol) and a global count
-//     of set R_C flags; barrier-based scheme -- max dr per iteration.
+// Work units:
+//   step   up to 256 vertices, four per lane.  Their in-rows are flattened
+//          into one edge range (prefix of the row lengths in LDS); every
+//          round each lane loads kUnroll row entries and then as many
+//          contributions C[u] = R[u] / (out-degree(u) + 1), all independent,
+//          and adds them to the owning row's LDS accumulator.  The implicit
+//          self-loop adds C[v].
+//   piece  up to kPiece consecutive in-edges of one long row (in-degree at
+//          or above split_min_degree; barrier-based scheme and static
+//          PageRank only), summed by a whole wavefront in registers; the
+//          wavefront completing the row's last piece adds the partial sums
+//          in piece order and finishes the vertex.
+//   finish r = (1 - alpha)/n + alpha * sum, dr = |r - R[v]|; when dr exceeds
+//          the frontier tolerance every out-neighbour is marked affected
+//          (once per vertex and update: flag bit kEX).
 //
 // Scheduling:
-//   k_df_async   one persistent launch.  A single 64-bit word holds the
-//                sweep index, a cursor into the current sweep's index space
-//                and the number of wavefronts holding a chunk.  Wavefronts
-//                grab chunks with fetch_add; the first to find the cursor at
-//                the end either starts the next sweep (some R_C still set)
-//                or, when no R_C is set and no chunk is held, ends the
-//                launch.  No grid barrier exists anywhere: sweeps overlap
-//                and ranks are updated in place (Algorithm 2's scheme).
+//   k_df_async   one persistent launch (lock-free scheme, Algorithm 2).  A
+//                64-bit word holds the sweep index, a cursor into the group
+//                worklist and the number of claims in flight; wavefronts
+//                claim groups with fetch_add and recompute their affected
+//                vertices in place.  A sweep ends the update when no claim
+//                is held and no claim of that sweep saw a change above the
+//                frontier tolerance (change_sweep watermark).  No grid
+//                barrier anywhere: sweeps overlap.
 //   k_sync_iter  one launch per iteration reading R/C and writing the other
-//                buffer (Algorithm 1); k_sync_finish ends the loop on the
-//                device so the host only polls every few iterations.
+//                buffer (Algorithm 1): wavefronts claim the iteration's
+//                pieces, then its edge-balanced steps; k_sync_finish ends
+//                the loop on the device so the host polls every few
+//                iterations.
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -64,11 +66,16 @@ struct RankArgs {
   int32_t *gwl;
   Ctl *ctl;
   double alpha, base, tol, ftol;
-  int32_t wave_min, kahan_min, chunk, max_iters;
+  int32_t split_min, kahan_min, chunk, max_iters;
   unsigned long long timeout_ticks;
   unsigned long long *sync_max;
   unsigned long long *sync_grab;
-  unsigned long long *sync_len;
+  unsigned long long *sync_len;  // per iteration: steps | pieces << 32
+  const int32_t *lrow;           // rows gathered in pieces (Split)
+  const int32_t *lpre;
+  const int32_t *prow;
+  double *ppart;
+  int32_t *lcnt;
 };
 
 struct Counters {
@@ -88,7 +95,7 @@ __device__ __forceinline__ T ldc(const T *C, int32_t u) {
 constexpr int kQ = 4;
 constexpr int kRows = kQ * kWave;
 // independent row entries (and then contributions) each lane loads per round
-constexpr int kUnroll = 4;
+constexpr int kUnroll = 8;
 
 // Per-wavefront LDS: the flattened edge list of the current step (prefix of
 // the row lengths and the row starts) and per-row accumulators.
@@ -247,29 +254,18 @@ __device__ __forceinline__ void expand_flat(const RankArgs<T> &A, WaveLds<T> &L,
   }
 }
 
-// Processes one step: four vertices per lane (v[k] < 0: empty slot).  All
-// 64 lanes call it.  `moved` is set when a rank changed by more than the
-// frontier tolerance; `maxdr` tracks the largest change.
+// Completes the step's vertices from their in-row sums (Eq. 1 with the
+// implicit self-loop): new rank and contribution, the change test against
+// the frontier tolerance, and the frontier expansion of vertices that moved
+// (v[k] < 0: empty slot; deg[k]: in-edges the caller's gather summed).  All
+// 64 lanes call it.
 template <typename T, int MODE>
-__device__ __forceinline__ void process_step(const RankArgs<T> &A, WaveLds<T> &L,
-                                             const int32_t *v, Counters &cnt,
-                                             double &maxdr, long long &newly,
-                                             bool &moved) {
+__device__ __forceinline__ void finish_rows(const RankArgs<T> &A, WaveLds<T> &L,
+                                            const int32_t *v, const int32_t *deg,
+                                            const double *sum, Counters &cnt,
+                                            double &maxdr, long long &newly,
+                                            bool &moved) {
   constexpr bool COH = MODE == kAsync;
-  int64_t off[kQ];
-  int32_t deg[kQ];
-#pragma unroll
-  for (int k = 0; k < kQ; ++k) {
-    off[k] = 0;
-    deg[k] = 0;
-    if (v[k] >= 0) {
-      off[k] = A.in_off[v[k]];
-      deg[k] = A.in_deg[v[k]];
-    }
-  }
-  double sum[kQ];
-  gather_flat<T, COH>(A, L, off, deg, sum);
-
   bool expand[kQ];
   int32_t od[kQ];
   int64_t oo[kQ];
@@ -318,6 +314,104 @@ __device__ __forceinline__ void process_step(const RankArgs<T> &A, WaveLds<T> &L
 #pragma unroll
   for (int k = 0; k < kQ; ++k)
     if (expand[k]) flag_set(A.flags, v[k], kEX);
+}
+
+// Processes one step: four vertices per lane (vin[k] < 0: empty slot).  All
+// 64 lanes call it.  `moved` is set when a rank changed by more than the
+// frontier tolerance; `maxdr` tracks the largest change.  Outside the
+// lock-free scheme, rows with at least split_min in-edges are left to the
+// piece path.
+template <typename T, int MODE>
+__device__ __forceinline__ void process_step(const RankArgs<T> &A, WaveLds<T> &L,
+                                             const int32_t *vin, Counters &cnt,
+                                             double &maxdr, long long &newly,
+                                             bool &moved) {
+  constexpr bool COH = MODE == kAsync;
+  int32_t v[kQ];
+  int64_t off[kQ];
+  int32_t deg[kQ];
+#pragma unroll
+  for (int k = 0; k < kQ; ++k) {
+    v[k] = vin[k];
+    off[k] = 0;
+    deg[k] = 0;
+    if (v[k] >= 0) {
+      const int32_t d = A.in_deg[v[k]];
+      if (MODE != kAsync && d >= A.split_min) {
+        v[k] = -1;
+      } else {
+        off[k] = A.in_off[v[k]];
+        deg[k] = d;
+      }
+    }
+  }
+  double sum[kQ];
+  gather_flat<T, COH>(A, L, off, deg, sum);
+  finish_rows<T, MODE>(A, L, v, deg, sum, cnt, maxdr, newly, moved);
+}
+
+// One piece of a long row (barrier-based scheme, static PageRank): the
+// wavefront sums up to kPiece consecutive in-edges of the row in registers
+// (fp64 for both rank types) and publishes the partial sum; the wavefront
+// that completes the row's last piece adds the row's partial sums in piece
+// order (so the result does not depend on which piece finished when) and
+// finishes the vertex.
+template <typename T, int MODE>
+__device__ void process_piece(const RankArgs<T> &A, WaveLds<T> &L, int32_t p,
+                              Counters &cnt, double &maxdr, long long &newly,
+                              bool &moved) {
+  const int lane = lane_id();
+  const int32_t j = __builtin_amdgcn_readfirstlane(A.prow[p]);
+  const int32_t v = __builtin_amdgcn_readfirstlane(A.lrow[j]);
+  const int32_t first = __builtin_amdgcn_readfirstlane(A.lpre[j]);
+  const int32_t np = __builtin_amdgcn_readfirstlane(A.lpre[j + 1]) - first;
+  const int32_t d = __builtin_amdgcn_readfirstlane(A.in_deg[v]);
+  const int32_t *row = A.in_adj + A.in_off[v];
+  const int32_t a = (p - first) * kPiece;
+  const int32_t b = a + kPiece < d ? a + kPiece : d;
+  double part = 0.0;
+  for (int32_t e0 = a; e0 < b; e0 += kUnroll * kWave) {
+    int32_t idx[kUnroll];
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) {
+      const int32_t e = e0 + q * kWave + lane;
+      idx[q] = e < b ? row[e] : -1;
+    }
+    T c[kUnroll];
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) c[q] = idx[q] >= 0 ? A.Cr[idx[q]] : (T)0;
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) part += (double)c[q];
+  }
+  part = wave_sum(part);
+  if (lane == 0) cnt.edges += (unsigned long long)(b - a);
+  double total = part;
+  if (np > 1) {
+    int last = 0;
+    if (lane == 0) {
+      store_agent(A.ppart + p, part);
+      const int32_t before = __hip_atomic_fetch_add(A.lcnt + j, 1, __ATOMIC_ACQ_REL,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+      last = before == np - 1;
+    }
+    if (!__builtin_amdgcn_readfirstlane(last)) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    double t = 0.0;
+    for (int32_t k = lane; k < np; k += kWave) t += load_agent(A.ppart + first + k);
+    total = wave_sum(t);
+    // every piece of the row has arrived: ready for the next iteration
+    if (lane == 0) store_agent(A.lcnt + j, 0);
+  }
+  int32_t vv[kQ];
+  int32_t dd[kQ];
+  double ss[kQ];
+#pragma unroll
+  for (int k = 0; k < kQ; ++k) {
+    vv[k] = (k == 0 && lane == 0) ? v : -1;
+    dd[k] = 0;
+    ss[k] = total;
+  }
+  finish_rows<T, MODE>(A, L, vv, dd, ss, cnt, maxdr, newly, moved);
 }
 
 template <typename T>
@@ -561,12 +655,23 @@ __global__ void __launch_bounds__(256) k_sync_iter(RankArgs<T> A, int iter,
   const int lane = lane_id();
   Counters cnt;
   double maxdr = 0.0;
-  const unsigned long long nsteps = A.sync_len[iter];
+  // pieces of long rows first (their finishing wavefronts may still have
+  // an out-row to mark), then the steps
+  const unsigned long long packed = A.sync_len[iter];
+  const unsigned long long npieces = packed >> 32;
+  const unsigned long long nitems = npieces + (packed & 0xFFFFFFFFull);
   while (true) {
     unsigned long long u = 0;
     if (lane == 0) u = atomicAdd(&A.sync_grab[iter], 1ull);
     u = bcast0(u);
-    if (u >= nsteps) break;
+    if (u >= nitems) break;
+    if (u < npieces) {
+      bool unused_moved = false;
+      long long unused_newly = 0;
+      process_piece<T, MODE>(A, L, (int32_t)u, cnt, maxdr, unused_newly, unused_moved);
+      continue;
+    }
+    u -= npieces;
     const int32_t start = steps[u], end = steps[u + 1];
     int32_t vv[kQ];
 #pragma unroll
@@ -594,7 +699,7 @@ __global__ void k_sync_finish(Ctl *ctl, const unsigned long long *sync_max,
     ctl->sync_final = iter + 1;
     ctl->sync_conv = md <= tol ? 1 : 0;
   } else {
-    sync_len[iter + 1] = ctl->nsteps;
+    sync_len[iter + 1] = ctl->nsteps | (ctl->npieces << 32);
   }
 }
 
@@ -608,7 +713,7 @@ __global__ void k_sync_begin(Ctl *ctl, unsigned long long *sync_max,
     sync_len[i] = 0;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    sync_len[0] = ctl->nsteps;
+    sync_len[0] = ctl->nsteps | (ctl->npieces << 32);
     ctl->sync_done = 0;
     ctl->sync_final = 0;
     ctl->sync_conv = 0;
@@ -852,7 +957,7 @@ RankArgs<T> make_args(dfpr_graph *g, int rd, int wr) {
   A.base = (1.0 - g->p.alpha) / (double)g->n;
   A.tol = g->p.tol;
   A.ftol = g->p.frontier_tol;
-  A.wave_min = g->p.wave_min_degree;
+  A.split_min = g->p.split_min_degree;
   A.kahan_min = g->p.kahan_min_degree;
   A.chunk = g->p.chunk;
   A.max_iters = g->p.max_iters;
@@ -862,6 +967,11 @@ RankArgs<T> make_args(dfpr_graph *g, int rd, int wr) {
   A.sync_max = g->sync_max;
   A.sync_grab = g->sync_grab;
   A.sync_len = g->sync_len;
+  A.lrow = g->split.lrow;
+  A.lpre = g->split.lpre;
+  A.prow = g->split.prow;
+  A.ppart = g->split.ppart;
+  A.lcnt = g->split.lcnt;
   return A;
 }
 
@@ -908,17 +1018,19 @@ int rebuild_worklist(dfpr_graph *g) {
   return DFPR_OK;
 }
 
-// in-edges a step aims at (a row is never split, so a step holding one
-// heavy row can exceed it)
+// in-edges a step aims at (rows below the split threshold are never split,
+// so a step can exceed it by up to one such row)
 constexpr int64_t kStepEdges = 16384;
 
 struct StepLen {
   const int32_t *list;  // worklist, or null for the identity (all vertices)
   const int32_t *deg;
   const unsigned long long *len;
+  int32_t split;        // rows at or above it count as one entry (pieces)
   __device__ int64_t operator()(int64_t i) const {
     if ((unsigned long long)i >= *len) return 0;
-    return (int64_t)deg[list ? list[i] : (int32_t)i] + 1;
+    const int32_t d = deg[list ? list[i] : (int32_t)i];
+    return d >= split ? 1 : (int64_t)d + 1;
   }
 };
 
@@ -932,6 +1044,34 @@ struct StepStart {
   }
 };
 
+struct ListId {
+  const int32_t *list;
+  __device__ int32_t operator()(int64_t i) const {
+    return list ? list[i] : (int32_t)i;
+  }
+};
+
+struct LongRow {
+  const int32_t *list;
+  const int32_t *deg;
+  const unsigned long long *len;
+  int32_t split;
+  __device__ uint8_t operator()(int64_t i) const {
+    if ((unsigned long long)i >= *len) return 0;
+    return deg[list ? list[i] : (int32_t)i] >= split ? 1 : 0;
+  }
+};
+
+struct PieceCount {
+  const int32_t *lrow;
+  const int32_t *deg;
+  const unsigned long long *nlong;
+  __device__ int32_t operator()(int64_t j) const {
+    if ((unsigned long long)j >= *nlong) return 0;
+    return (deg[lrow[j]] + kPiece - 1) / kPiece;
+  }
+};
+
 __global__ void k_steps_sentinel(int32_t *steps, const unsigned long long *nsteps,
                                  const unsigned long long *len) {
   if (threadIdx.x == 0 && blockIdx.x == 0) steps[*nsteps] = (int32_t)*len;
@@ -941,15 +1081,58 @@ __global__ void k_set_len(unsigned long long *dst, unsigned long long v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *dst = v;
 }
 
-// Cuts the first *len entries of `list` (or of the identity) into steps:
-// a step starts every 256 entries and wherever the running in-edge count
-// crosses a multiple of kStepEdges.  Writes g->steps[0 .. nsteps] and
-// ctl->nsteps on the device.
+// Piece table: prow[p] = long row of piece p; ctl->npieces.
+__global__ void k_fill_pieces(const int32_t *lpre, int32_t *prow, Ctl *ctl) {
+  const unsigned long long nl = ctl->nlong;
+  for (unsigned long long j = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x;
+       j < nl; j += (unsigned long long)gridDim.x * blockDim.x) {
+    const int32_t p0 = lpre[j], p1 = lpre[j + 1];
+    for (int32_t p = p0; p < p1; ++p) prow[p] = (int32_t)j;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->npieces = (unsigned long long)lpre[nl];
+}
+
+// Sizes the piece arrays for the current adjacency capacity and threshold:
+// a row with at least split_min in-edges holds that many slots, so at most
+// adj_cap / split_min rows are long, and they have at most
+// adj_cap / kPiece + (long rows) pieces.
+int ensure_split(dfpr_graph *g) {
+  Split &S = g->split;
+  int64_t lcap = g->in.adj_cap / g->p.split_min_degree + 1;
+  if (lcap > (int64_t)g->n + 1) lcap = (int64_t)g->n + 1;
+  const int64_t pcap = g->in.adj_cap / kPiece + lcap + 1;
+  if (lcap <= S.lcap && pcap <= S.pcap) return DFPR_OK;
+  DFPR_HIP(hipStreamSynchronize(g->stream));
+  void *old[] = {S.lrow, S.lpre, S.lcnt, S.prow, S.ppart};
+  for (void *p : old)
+    if (p) DFPR_HIP(hipFree(p));
+  S = Split();
+  DFPR_HIP(hipMalloc(&S.lrow, (size_t)lcap * 4));
+  DFPR_HIP(hipMalloc(&S.lpre, (size_t)(lcap + 1) * 4));
+  DFPR_HIP(hipMalloc(&S.lcnt, (size_t)lcap * 4));
+  DFPR_HIP(hipMalloc(&S.prow, (size_t)pcap * 4));
+  DFPR_HIP(hipMalloc(&S.ppart, (size_t)pcap * 8));
+  DFPR_HIP(hipMemsetAsync(S.lcnt, 0, (size_t)lcap * 4, g->stream));
+  S.lcap = lcap;
+  S.pcap = pcap;
+  return DFPR_OK;
+}
+
+// Cuts the first *len entries of `list` (or of the identity) into work
+// items for one barrier-based iteration:
+//   steps: a step starts every 256 entries and wherever the running in-edge
+//     count crosses a multiple of kStepEdges (rows at or above the split
+//     threshold count as one entry); g->steps[0 .. nsteps], ctl->nsteps.
+//   pieces: the rows at or above the threshold (split.lrow, ctl->nlong),
+//     their first pieces (split.lpre) and the piece table (split.prow,
+//     ctl->npieces).
 int build_steps(dfpr_graph *g, const int32_t *list, const unsigned long long *len) {
   hipStream_t s = g->stream;
   const size_t n = (size_t)g->n;
+  const int32_t split = g->p.split_min_degree;
+  Split &S = g->split;
   rocprim::counting_iterator<int64_t> idx(0);
-  auto lens = rocprim::make_transform_iterator(idx, StepLen{list, g->in.deg, len});
+  auto lens = rocprim::make_transform_iterator(idx, StepLen{list, g->in.deg, len, split});
   size_t tb = 0;
   DFPR_HIP(rocprim::exclusive_scan(nullptr, tb, lens, g->epre, (int64_t)0, n,
                                    rocprim::plus<int64_t>(), s));
@@ -966,6 +1149,23 @@ int build_steps(dfpr_graph *g, const int32_t *list, const unsigned long long *le
   DFPR_HIP(rocprim::select(tmp, tb, pos, starts, g->steps, &g->ctl->nsteps, n, s));
   k_steps_sentinel<<<1, 64, 0, s>>>(g->steps, &g->ctl->nsteps, len);
   DFPR_HIP(hipGetLastError());
+
+  auto ids = rocprim::make_transform_iterator(idx, ListId{list});
+  auto longf = rocprim::make_transform_iterator(idx, LongRow{list, g->in.deg, len, split});
+  tb = 0;
+  DFPR_HIP(rocprim::select(nullptr, tb, ids, longf, S.lrow, &g->ctl->nlong, n, s));
+  if ((rc = scratch_get(g, 14, tb, &tmp))) return rc;
+  DFPR_HIP(rocprim::select(tmp, tb, ids, longf, S.lrow, &g->ctl->nlong, n, s));
+  auto counts = rocprim::make_transform_iterator(
+      idx, PieceCount{S.lrow, g->in.deg, &g->ctl->nlong});
+  tb = 0;
+  DFPR_HIP(rocprim::exclusive_scan(nullptr, tb, counts, S.lpre, (int32_t)0,
+                                   (size_t)S.lcap + 1, rocprim::plus<int32_t>(), s));
+  if ((rc = scratch_get(g, 14, tb, &tmp))) return rc;
+  DFPR_HIP(rocprim::exclusive_scan(tmp, tb, counts, S.lpre, (int32_t)0,
+                                   (size_t)S.lcap + 1, rocprim::plus<int32_t>(), s));
+  k_fill_pieces<<<grid_for(S.lcap, g->cu_count), 256, 0, s>>>(S.lpre, S.prow, g->ctl);
+  DFPR_HIP(hipGetLastError());
   return DFPR_OK;
 }
 
@@ -981,7 +1181,8 @@ int run_sync(dfpr_graph *g, int mode, dfpr_stats *st) {
                             hipMemcpyDeviceToDevice, s));
   }
   {
-    int rc;
+    int rc = ensure_split(g);
+    if (rc) return rc;
     if (mode != kAll) {
       if ((rc = rebuild_worklist(g))) return rc;
       if ((rc = build_steps(g, g->wl, &g->ctl->tail))) return rc;

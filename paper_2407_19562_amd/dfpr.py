@@ -48,7 +48,7 @@ class dfpr_params(ctypes.Structure):
                 ("frontier_tol", ctypes.c_double),
                 ("max_iters", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("mode", ctypes.c_int32), ("kahan_min_degree", ctypes.c_int32),
-                ("wave_min_degree", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("split_min_degree", ctypes.c_int32), ("chunk", ctypes.c_int32),
                 ("block_size", ctypes.c_int32), ("reorder", ctypes.c_int32),
                 ("renormalize", ctypes.c_int32), ("timeout_ms", ctypes.c_int32),
                 ("grid_blocks", ctypes.c_int32)]

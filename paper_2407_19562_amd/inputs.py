@@ -265,6 +265,25 @@ def road_grid(seed: int = 3, side: int = 4096):
     return grid_road(side, seed)
 
 
+def heavy_rows(seed: int = 5, n: int = 30000, avg_degree: int = 4,
+               hub_in=(4095, 4096, 4097, 8192, 12289, 25000)):
+    """G(n, m) with average degree `avg_degree`, plus hubs 0..len(hub_in)-1
+    whose in-degrees are exactly the listed values (edges from distinct
+    random sources) (rows just below, at and above the 4096-edge piece size
+    and several pieces long).  Returns (n, src, dst) without duplicates."""
+    rng = np.random.default_rng(seed)
+    n0, s0, d0 = erdos_renyi(n, n * avg_degree, seed)
+    keep = d0 >= len(hub_in)             # hubs get only the edges below
+    keys = [s0[keep].astype(np.int64) * n + d0[keep]]
+    for h, k in enumerate(hub_in):
+        src = rng.choice(n, size=k + 1, replace=False)
+        src = src[src != h][:k]
+        keys.append(src.astype(np.int64) * n + h)
+    keys = np.unique(np.concatenate(keys))
+    keys = rng.permutation(keys)
+    return n, (keys // n).astype(np.int32), (keys % n).astype(np.int32)
+
+
 def graph_mix(count: int, seed: int, m_lo: float = 1e3, m_hi: float = 1e6,
               deg_lo: float = 4, deg_hi: float = 32):
     """Many small graphs: edge counts log-uniform in [m_lo, m_hi], average

@@ -225,6 +225,57 @@ def test_df_fp64_matches_oracle(D, O, mode, frac, reorder):
         assert abs(st.affected - int(res.affected.sum())) <= max(3, res.affected.sum() // 1000)
 
 
+@pytest.mark.parametrize("split", [1, 64, 2048, 1 << 30])
+@pytest.mark.parametrize("prec", [64, 32])
+def test_split_rows_match_oracle(D, O, split, prec):
+    # rows summed in pieces (in-degrees 4095..25000: one to seven pieces)
+    # next to rows summed in steps; split = 1: every row in pieces,
+    # 1 << 30: none
+    say("split rows", split, prec)
+    n, s, d = inputs.heavy_rows()
+    R0, _, _ = O.pagerank(n, s, d)
+    b = inputs.batches(n, s, d, 1, 77, frac=1e-3)[0]
+    ns, nd, res, ndel, nins = O.update(n, s, d, b, R0)
+    ref, _, _ = O.pagerank(n, ns, nd)
+    with graph(D, n, s, d, mode=D.DFPR_SYNC, precision=prec,
+               renormalize=int(prec == 32), split_min_degree=split) as g:
+        rc, st = g.static()
+        assert rc == D.DFPR_OK and st.converged
+        Rs = g.ranks()
+        g.set_ranks(R0)
+        assert g.apply(b) == (ndel, nins)
+        rc, st = g.update()
+        assert rc == D.DFPR_OK and st.converged, st.as_dict()
+        R = g.ranks()
+    say("  static err", err64(Rs, R0), "update err", err64(R, ref), "iters",
+        st.sweeps, "oracle", res.iters)
+    if prec == 64:
+        assert err64(Rs, R0) < FP64_TOL
+        assert err64(R, ref) < FP64_TOL
+        assert abs(st.sweeps - res.iters) <= 1
+    else:
+        assert rel32(Rs, R0) < FP32_REL
+        assert rel32(R, ref) < FP32_REL
+
+
+def test_sync_update_is_deterministic(D, O):
+    # piece sums are added in piece order and every step row is summed by
+    # one wavefront, so repeated runs give the same bits
+    say("determinism")
+    n, s, d = inputs.heavy_rows()
+    R0, _, _ = O.pagerank(n, s, d)
+    b = inputs.batches(n, s, d, 1, 78, frac=1e-2)[0]
+    out = []
+    for _ in range(2):
+        with graph(D, n, s, d, mode=D.DFPR_SYNC, split_min_degree=64) as g:
+            g.set_ranks(R0)
+            g.apply(b)
+            rc, st = g.update()
+            assert rc == D.DFPR_OK
+            out.append(g.ranks())
+    assert np.array_equal(out[0], out[1])
+
+
 @pytest.mark.parametrize("mode", ["sync", "async"])
 def test_df_fp32_matches_oracle(D, O, mode):
     say("df fp32", mode)
@@ -245,7 +296,7 @@ def test_df_fp32_matches_oracle(D, O, mode):
 
 
 @pytest.mark.parametrize("mode", ["sync", "async"])
-@pytest.mark.parametrize("k", [7, 1000, 5000])
+@pytest.mark.parametrize("k", [7, 1000, 5000, 20000])
 def test_df_star_closed_form(D, O, mode, k):
     say("star", mode, k)
     # out-star -> bidirectional star; the closed forms fix both ends
