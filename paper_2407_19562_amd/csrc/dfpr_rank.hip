@@ -1001,95 +1001,130 @@ double algorithmic_bytes(const dfpr_graph *g, const Ctl &h) {
   return 8.0 * e + 36.0 * (double)h.vertices + 5.0 * (double)h.out_scanned;
 }
 
-// Rebuilds the vertex worklist from the affected flags, in vertex-id order
-// (every nonzero flag byte belongs to an affected vertex); the count lands
-// in ctl->tail on the device.  Consecutive ids keep the row, offset and
-// rank accesses of a step nearly contiguous.
-int rebuild_worklist(dfpr_graph *g) {
-  hipStream_t s = g->stream;
-  const uint8_t *fl = reinterpret_cast<const uint8_t *>(g->flags);
-  rocprim::counting_iterator<int32_t> ids(0);
-  size_t tb = 0;
-  DFPR_HIP(rocprim::select(nullptr, tb, ids, fl, g->wl, &g->ctl->tail, (size_t)g->n, s));
-  void *tmp = nullptr;
-  int rc = scratch_get(g, 14, tb, &tmp);
-  if (rc) return rc;
-  DFPR_HIP(rocprim::select(tmp, tb, ids, fl, g->wl, &g->ctl->tail, (size_t)g->n, s));
-  return DFPR_OK;
+// Work items of one barrier-based iteration, built from the affected flags
+// (or from every vertex, for static PageRank) in three launches: per-tile
+// counts, a scan over tiles, and an emit pass.  A tile is kRows consecutive
+// vertex ids; its selected vertices keep id order.
+//   worklist  wl[0 .. tail) (affected vertices; not written for static)
+//   steps     worklist positions where a step starts, plus a sentinel: a
+//             step never crosses a tile, starts at the tile's first
+//             selected vertex and at every vertex whose in-edges reach past
+//             a multiple of kStepEdges of the tile's running count
+//   pieces    rows with at least split_min in-edges count as one entry in
+//             the steps and are summed in pieces of kPiece in-edges:
+//             split.lrow (their ids), split.lpre (first piece of each),
+//             split.prow (long row of each piece)
+// Totals land in ctl->tail / nsteps / nlong / npieces.  Rows of fewer
+// in-edges are never split, so a step can exceed kStepEdges by one row.
+constexpr int32_t kStepEdges = 16384;
+
+struct TileSum {
+  int32_t sel, steps, nlong, pieces;
+};
+
+struct TileSumPlus {
+  __device__ __host__ TileSum operator()(const TileSum &a, const TileSum &b) const {
+    return TileSum{a.sel + b.sel, a.steps + b.steps, a.nlong + b.nlong, a.pieces + b.pieces};
+  }
+};
+
+// Exclusive block-wide prefix of x over the 256 threads; *total = sum.
+__device__ __forceinline__ int32_t block_excl_scan(int32_t x, int32_t *lds4,
+                                                   int32_t *total) {
+  const int lane = lane_id();
+  const int w = threadIdx.x / kWave;
+  const int32_t incl = wave_incl_scan(x);
+  __syncthreads();
+  if (lane == kWave - 1) lds4[w] = incl;
+  __syncthreads();
+  int32_t before = 0, sum = 0;
+#pragma unroll
+  for (int i = 0; i < 256 / kWave; ++i) {
+    const int32_t t = lds4[i];
+    before += i < w ? t : 0;
+    sum += t;
+  }
+  *total = sum;
+  return before + incl - x;
 }
 
-// in-edges a step aims at (rows below the split threshold are never split,
-// so a step can exceed it by up to one such row)
-constexpr int64_t kStepEdges = 16384;
-
-struct StepLen {
-  const int32_t *list;  // worklist, or null for the identity (all vertices)
-  const int32_t *deg;
-  const unsigned long long *len;
-  int32_t split;        // rows at or above it count as one entry (pieces)
-  __device__ int64_t operator()(int64_t i) const {
-    if ((unsigned long long)i >= *len) return 0;
-    const int32_t d = deg[list ? list[i] : (int32_t)i];
-    return d >= split ? 1 : (int64_t)d + 1;
-  }
+struct TileScan {
+  int32_t v;       // vertex id (valid when sel)
+  bool sel, start, is_long;
+  int32_t rank;    // position among the tile's selected vertices
+  int32_t srank;   // position among the tile's step starts
+  int32_t lrank;   // position among the tile's long rows
+  int32_t ppre;    // first piece among the tile's pieces
+  int32_t npieces; // pieces of this row
+  TileSum tot;
 };
 
-struct StepStart {
-  const int64_t *pre;
-  const unsigned long long *len;
-  __device__ uint8_t operator()(int64_t i) const {
-    if ((unsigned long long)i >= *len) return 0;
-    if ((i & (kRows - 1)) == 0) return 1;
-    return (pre[i] / kStepEdges) != (pre[i - 1] / kStepEdges) ? 1 : 0;
-  }
-};
-
-struct ListId {
-  const int32_t *list;
-  __device__ int32_t operator()(int64_t i) const {
-    return list ? list[i] : (int32_t)i;
-  }
-};
-
-struct LongRow {
-  const int32_t *list;
-  const int32_t *deg;
-  const unsigned long long *len;
-  int32_t split;
-  __device__ uint8_t operator()(int64_t i) const {
-    if ((unsigned long long)i >= *len) return 0;
-    return deg[list ? list[i] : (int32_t)i] >= split ? 1 : 0;
-  }
-};
-
-struct PieceCount {
-  const int32_t *lrow;
-  const int32_t *deg;
-  const unsigned long long *nlong;
-  __device__ int32_t operator()(int64_t j) const {
-    if ((unsigned long long)j >= *nlong) return 0;
-    return (deg[lrow[j]] + kPiece - 1) / kPiece;
-  }
-};
-
-__global__ void k_steps_sentinel(int32_t *steps, const unsigned long long *nsteps,
-                                 const unsigned long long *len) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) steps[*nsteps] = (int32_t)*len;
+// One tile per 256-thread block, one vertex per thread.
+template <bool ALL>
+__device__ __forceinline__ TileScan tile_scan(const uint8_t *flags,
+                                              const int32_t *deg, int32_t n,
+                                              int32_t split) {
+  __shared__ int32_t lds4[4];
+  TileScan r;
+  r.v = (int32_t)blockIdx.x * kRows + (int32_t)threadIdx.x;
+  r.sel = r.v < n && (ALL || flags[r.v] != 0);
+  const int32_t d = r.sel ? deg[r.v] : 0;
+  r.is_long = r.sel && d >= split;
+  const int32_t len = r.sel ? (r.is_long ? 1 : d + 1) : 0;
+  r.npieces = r.is_long ? (d + kPiece - 1) / kPiece : 0;
+  int32_t tsel, tlen, tlong, tpieces, tsteps;
+  r.rank = block_excl_scan(r.sel ? 1 : 0, lds4, &tsel);
+  const int32_t y = block_excl_scan(len, lds4, &tlen);
+  // a step starts at the first selected vertex and at every vertex whose
+  // in-edges reach past a multiple of kStepEdges of the running count
+  r.start = r.sel && (r.rank == 0 || (y + len - 1) / kStepEdges != (y - 1) / kStepEdges);
+  r.srank = block_excl_scan(r.start ? 1 : 0, lds4, &tsteps);
+  r.lrank = block_excl_scan(r.is_long ? 1 : 0, lds4, &tlong);
+  r.ppre = block_excl_scan(r.npieces, lds4, &tpieces);
+  r.tot = TileSum{tsel, tsteps, tlong, tpieces};
+  return r;
 }
 
-__global__ void k_set_len(unsigned long long *dst, unsigned long long v) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = v;
+template <bool ALL>
+__global__ void __launch_bounds__(256) k_tile_count(const uint8_t *flags,
+                                                    const int32_t *deg, int32_t n,
+                                                    int32_t split, TileSum *sums) {
+  const TileScan r = tile_scan<ALL>(flags, deg, n, split);
+  if (threadIdx.x == 0) {
+    sums[blockIdx.x] = r.tot;
+    if (blockIdx.x == gridDim.x - 1) sums[gridDim.x] = TileSum{0, 0, 0, 0};
+  }
 }
 
-// Piece table: prow[p] = long row of piece p; ctl->npieces.
-__global__ void k_fill_pieces(const int32_t *lpre, int32_t *prow, Ctl *ctl) {
-  const unsigned long long nl = ctl->nlong;
-  for (unsigned long long j = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x;
-       j < nl; j += (unsigned long long)gridDim.x * blockDim.x) {
-    const int32_t p0 = lpre[j], p1 = lpre[j + 1];
-    for (int32_t p = p0; p < p1; ++p) prow[p] = (int32_t)j;
+template <bool ALL>
+__global__ void __launch_bounds__(256) k_tile_emit(const uint8_t *flags,
+                                                   const int32_t *deg, int32_t n,
+                                                   int32_t split, const TileSum *pre,
+                                                   int32_t *wl, int32_t *steps,
+                                                   Split S, Ctl *ctl) {
+  const TileScan r = tile_scan<ALL>(flags, deg, n, split);
+  const TileSum b = pre[blockIdx.x];
+  if (r.sel) {
+    const int32_t pos = b.sel + r.rank;
+    if (!ALL) wl[pos] = r.v;
+    if (r.start) steps[b.steps + r.srank] = pos;
+    if (r.is_long) {
+      const int32_t j = b.nlong + r.lrank;
+      const int32_t p0 = b.pieces + r.ppre;
+      S.lrow[j] = r.v;
+      S.lpre[j] = p0;
+      for (int32_t k = 0; k < r.npieces; ++k) S.prow[p0 + k] = j;
+    }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->npieces = (unsigned long long)lpre[nl];
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+    const TileSum t = pre[gridDim.x];
+    if (!ALL) ctl->tail = (unsigned long long)t.sel;
+    ctl->nsteps = (unsigned long long)t.steps;
+    ctl->nlong = (unsigned long long)t.nlong;
+    ctl->npieces = (unsigned long long)t.pieces;
+    steps[t.steps] = t.sel;
+    S.lpre[t.nlong] = t.pieces;
+  }
 }
 
 // Sizes the piece arrays for the current adjacency capacity and threshold:
@@ -1118,53 +1153,42 @@ int ensure_split(dfpr_graph *g) {
   return DFPR_OK;
 }
 
-// Cuts the first *len entries of `list` (or of the identity) into work
-// items for one barrier-based iteration:
-//   steps: a step starts every 256 entries and wherever the running in-edge
-//     count crosses a multiple of kStepEdges (rows at or above the split
-//     threshold count as one entry); g->steps[0 .. nsteps], ctl->nsteps.
-//   pieces: the rows at or above the threshold (split.lrow, ctl->nlong),
-//     their first pieces (split.lpre) and the piece table (split.prow,
-//     ctl->npieces).
-int build_steps(dfpr_graph *g, const int32_t *list, const unsigned long long *len) {
+// Builds the work items of the next barrier-based iteration (all = true:
+// every vertex, static PageRank).
+int build_items(dfpr_graph *g, bool all) {
   hipStream_t s = g->stream;
-  const size_t n = (size_t)g->n;
-  const int32_t split = g->p.split_min_degree;
-  Split &S = g->split;
-  rocprim::counting_iterator<int64_t> idx(0);
-  auto lens = rocprim::make_transform_iterator(idx, StepLen{list, g->in.deg, len, split});
-  size_t tb = 0;
-  DFPR_HIP(rocprim::exclusive_scan(nullptr, tb, lens, g->epre, (int64_t)0, n,
-                                   rocprim::plus<int64_t>(), s));
-  void *tmp = nullptr;
-  int rc = scratch_get(g, 14, tb, &tmp);
+  if (g->n == 0) {
+    DFPR_HIP(hipMemsetAsync(&g->ctl->tail, 0, 4 * sizeof(unsigned long long), s));
+    return DFPR_OK;
+  }
+  const int32_t nt = (g->n + kRows - 1) / kRows;
+  const size_t tbytes = sizeof(TileSum) * ((size_t)nt + 1);
+  void *buf = nullptr;
+  int rc = scratch_get(g, 15, 2 * tbytes, &buf);
   if (rc) return rc;
-  DFPR_HIP(rocprim::exclusive_scan(tmp, tb, lens, g->epre, (int64_t)0, n,
-                                   rocprim::plus<int64_t>(), s));
-  auto starts = rocprim::make_transform_iterator(idx, StepStart{g->epre, len});
-  rocprim::counting_iterator<int32_t> pos(0);
-  tb = 0;
-  DFPR_HIP(rocprim::select(nullptr, tb, pos, starts, g->steps, &g->ctl->nsteps, n, s));
-  if ((rc = scratch_get(g, 14, tb, &tmp))) return rc;
-  DFPR_HIP(rocprim::select(tmp, tb, pos, starts, g->steps, &g->ctl->nsteps, n, s));
-  k_steps_sentinel<<<1, 64, 0, s>>>(g->steps, &g->ctl->nsteps, len);
+  TileSum *sums = (TileSum *)buf;
+  TileSum *pre = (TileSum *)((char *)buf + tbytes);
+  const uint8_t *fl = reinterpret_cast<const uint8_t *>(g->flags);
+  const int32_t split = g->p.split_min_degree;
+  if (all)
+    k_tile_count<true><<<nt, 256, 0, s>>>(fl, g->in.deg, g->n, split, sums);
+  else
+    k_tile_count<false><<<nt, 256, 0, s>>>(fl, g->in.deg, g->n, split, sums);
   DFPR_HIP(hipGetLastError());
-
-  auto ids = rocprim::make_transform_iterator(idx, ListId{list});
-  auto longf = rocprim::make_transform_iterator(idx, LongRow{list, g->in.deg, len, split});
-  tb = 0;
-  DFPR_HIP(rocprim::select(nullptr, tb, ids, longf, S.lrow, &g->ctl->nlong, n, s));
+  size_t tb = 0;
+  const TileSum zero{0, 0, 0, 0};
+  DFPR_HIP(rocprim::exclusive_scan(nullptr, tb, sums, pre, zero, (size_t)nt + 1,
+                                   TileSumPlus(), s));
+  void *tmp = nullptr;
   if ((rc = scratch_get(g, 14, tb, &tmp))) return rc;
-  DFPR_HIP(rocprim::select(tmp, tb, ids, longf, S.lrow, &g->ctl->nlong, n, s));
-  auto counts = rocprim::make_transform_iterator(
-      idx, PieceCount{S.lrow, g->in.deg, &g->ctl->nlong});
-  tb = 0;
-  DFPR_HIP(rocprim::exclusive_scan(nullptr, tb, counts, S.lpre, (int32_t)0,
-                                   (size_t)S.lcap + 1, rocprim::plus<int32_t>(), s));
-  if ((rc = scratch_get(g, 14, tb, &tmp))) return rc;
-  DFPR_HIP(rocprim::exclusive_scan(tmp, tb, counts, S.lpre, (int32_t)0,
-                                   (size_t)S.lcap + 1, rocprim::plus<int32_t>(), s));
-  k_fill_pieces<<<grid_for(S.lcap, g->cu_count), 256, 0, s>>>(S.lpre, S.prow, g->ctl);
+  DFPR_HIP(rocprim::exclusive_scan(tmp, tb, sums, pre, zero, (size_t)nt + 1,
+                                   TileSumPlus(), s));
+  if (all)
+    k_tile_emit<true><<<nt, 256, 0, s>>>(fl, g->in.deg, g->n, split, pre, g->wl, g->steps,
+                                         g->split, g->ctl);
+  else
+    k_tile_emit<false><<<nt, 256, 0, s>>>(fl, g->in.deg, g->n, split, pre, g->wl, g->steps,
+                                          g->split, g->ctl);
   DFPR_HIP(hipGetLastError());
   return DFPR_OK;
 }
@@ -1183,15 +1207,7 @@ int run_sync(dfpr_graph *g, int mode, dfpr_stats *st) {
   {
     int rc = ensure_split(g);
     if (rc) return rc;
-    if (mode != kAll) {
-      if ((rc = rebuild_worklist(g))) return rc;
-      if ((rc = build_steps(g, g->wl, &g->ctl->tail))) return rc;
-    } else {
-      // static: every vertex, in id order; the length lives in sync_max[0]
-      // until k_sync_begin clears it
-      k_set_len<<<1, 64, 0, s>>>(g->sync_max, (unsigned long long)g->n);
-      if ((rc = build_steps(g, nullptr, g->sync_max))) return rc;
-    }
+    if ((rc = build_items(g, mode == kAll))) return rc;
   }
   k_sync_begin<<<4, 256, 0, s>>>(g->ctl, g->sync_max, g->sync_grab, g->sync_len, iters);
   DFPR_HIP(hipGetLastError());
@@ -1204,9 +1220,8 @@ int run_sync(dfpr_graph *g, int mode, dfpr_stats *st) {
     RankArgs<T> A = make_args<T>(g, (g->cur + it) & 1, (g->cur + it + 1) & 1);
     kern<<<blocks, g->p.block_size, 0, s>>>(A, it, g->steps);
     if (mode != kAll) {
-      int rc = rebuild_worklist(g);
+      int rc = build_items(g, false);
       if (rc) return rc;
-      if ((rc = build_steps(g, g->wl, &g->ctl->tail))) return rc;
     }
     k_sync_finish<<<1, 64, 0, s>>>(g->ctl, g->sync_max, g->sync_len, it, g->p.tol,
                                    iters, mode == kSyncDF);
