@@ -120,7 +120,7 @@ static int alloc_graph(dfpr_graph *g) {
   DFPR_HIP(hipMemsetAsync(g->ctl, 0, sizeof(Ctl), g->stream));
   DFPR_HIP(hipHostMalloc(&g->h_ctl, sizeof(Ctl), hipHostMallocDefault));
   DFPR_HIP(hipMalloc(&g->sync_max, kMaxIters * 8));
-  DFPR_HIP(hipMalloc(&g->sync_grab, kMaxIters * 8));
+  DFPR_HIP(hipMalloc(&g->sync_grab, kClaimers * kClaimStride * 8));
   DFPR_HIP(hipMalloc(&g->sync_len, kMaxIters * 8));
   for (auto &e : g->ev) DFPR_HIP(hipEventCreate(&e));
   return DFPR_OK;

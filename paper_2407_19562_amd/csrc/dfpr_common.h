@@ -52,6 +52,12 @@ constexpr int kCursorShift = 16;
 constexpr uint64_t kCursorMask = 0xFFFFFFFFull;
 constexpr uint64_t kInflightMask = 0xFFFFull;
 
+// Claim counters of the barrier-based iteration (unsigned long long, 128
+// bytes apart); wavefront w claims the items c + kClaimers * k from counter
+// c = w % kClaimers.
+constexpr int kClaimers = 16;
+constexpr int kClaimStride = 16;
+
 // Device control block of one graph.  The words every wavefront of the
 // persistent kernel touches sit on cache lines of their own.
 struct Ctl {
@@ -139,7 +145,8 @@ struct dfpr_graph {
   dfpr::Ctl *ctl = nullptr;
   dfpr::Ctl *h_ctl = nullptr;           // pinned host mirror
   unsigned long long *sync_max = nullptr;   // [kMaxIters] bit patterns
-  unsigned long long *sync_grab = nullptr;  // [kMaxIters] chunk tickets
+  unsigned long long *sync_grab = nullptr;  // claim counters of the
+                                            // barrier-based iteration
   unsigned long long *sync_len = nullptr;   // [kMaxIters] worklist snapshot
   int64_t pending_marks = 0;  // host view of marks not yet consumed
   dfpr::Scratch scratch[16];

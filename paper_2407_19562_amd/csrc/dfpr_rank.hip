@@ -660,9 +660,14 @@ __global__ void __launch_bounds__(256) k_sync_iter(RankArgs<T> A, int iter,
   const unsigned long long packed = A.sync_len[iter];
   const unsigned long long npieces = packed >> 32;
   const unsigned long long nitems = npieces + (packed & 0xFFFFFFFFull);
+  // claims are spread over kClaimers counters (item c + kClaimers * k from
+  // counter c): one hot counter serialised ~20K claims per C2 iteration
+  const unsigned wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const unsigned c = wave % kClaimers;
+  unsigned long long *ctr = A.sync_grab + c * kClaimStride;
   while (true) {
     unsigned long long u = 0;
-    if (lane == 0) u = atomicAdd(&A.sync_grab[iter], 1ull);
+    if (lane == 0) u = c + kClaimers * atomicAdd(ctr, 1ull);
     u = bcast0(u);
     if (u >= nitems) break;
     if (u < npieces) {
@@ -690,8 +695,10 @@ __global__ void __launch_bounds__(256) k_sync_iter(RankArgs<T> A, int iter,
 }
 
 __global__ void k_sync_finish(Ctl *ctl, const unsigned long long *sync_max,
-                              unsigned long long *sync_len, int iter,
+                              unsigned long long *sync_len,
+                              unsigned long long *claims, int iter,
                               double tol, int max_iters, int df) {
+  if (threadIdx.x < kClaimers) claims[threadIdx.x * kClaimStride] = 0;
   if (threadIdx.x != 0 || ctl->sync_done) return;
   const double md = __longlong_as_double((long long)sync_max[iter]);
   if (md <= tol || iter + 1 >= max_iters) {
@@ -709,9 +716,9 @@ __global__ void k_sync_begin(Ctl *ctl, unsigned long long *sync_max,
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < iters;
        i += gridDim.x * blockDim.x) {
     sync_max[i] = 0;
-    sync_grab[i] = 0;
     sync_len[i] = 0;
   }
+  if (blockIdx.x == 0 && threadIdx.x < kClaimers) sync_grab[threadIdx.x * kClaimStride] = 0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     sync_len[0] = ctl->nsteps | (ctl->npieces << 32);
     ctl->sync_done = 0;
@@ -1223,8 +1230,8 @@ int run_sync(dfpr_graph *g, int mode, dfpr_stats *st) {
       int rc = build_items(g, false);
       if (rc) return rc;
     }
-    k_sync_finish<<<1, 64, 0, s>>>(g->ctl, g->sync_max, g->sync_len, it, g->p.tol,
-                                   iters, mode == kSyncDF);
+    k_sync_finish<<<1, 64, 0, s>>>(g->ctl, g->sync_max, g->sync_len, g->sync_grab, it,
+                                   g->p.tol, iters, mode == kSyncDF);
     if ((it + 1) % poll == 0 || it + 1 == iters) {
       DFPR_HIP(hipGetLastError());
       DFPR_HIP(hipMemcpyAsync(g->h_ctl, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
