@@ -80,7 +80,7 @@ static void release(dfpr_graph *g) {
                   g->sync_grab, g->sync_len, g->gflags, g->gwl,
                   g->ext2int, g->int2ext, g->steps, g->epre,
                   g->split.lrow, g->split.lpre, g->split.lcnt, g->split.prow,
-                  g->split.ppart};
+                  g->split.ppart, g->split.xrow};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (auto &s : g->scratch)

@@ -66,6 +66,7 @@ struct Ctl {
   unsigned long long nsteps;              // steps of the current worklist
   unsigned long long nlong;               // rows gathered in pieces
   unsigned long long npieces;             // their pieces
+  unsigned long long nexp;                // long out-rows left to mark
   alignas(128) unsigned long long gtail;  // group worklist length
   alignas(128) long long change_sweep;    // last sweep in which a claim saw a
                                           // change above the frontier tol
@@ -110,7 +111,9 @@ struct Split {
   int32_t *lcnt = nullptr;  // [lcap] pieces of row j finished (the last resets it)
   int32_t *prow = nullptr;  // [pcap] long row of piece p
   double *ppart = nullptr;  // [pcap] partial sum of piece p
-  int64_t lcap = 0, pcap = 0;
+  int32_t *xrow = nullptr;  // [xcap] vertices whose long out-rows are marked
+                            // after the iteration (Ctl::nexp entries)
+  int64_t lcap = 0, pcap = 0, xcap = 0;
 };
 
 // Reusable device scratch of apply_batch (grown on demand).

@@ -76,6 +76,7 @@ struct RankArgs {
   const int32_t *prow;
   double *ppart;
   int32_t *lcnt;
+  int32_t *xrow;                 // deferred long out-rows (Split)
 };
 
 struct Counters {
@@ -248,7 +249,7 @@ __device__ __forceinline__ void expand_flat(const RankArgs<T> &A, WaveLds<T> &L,
         newly += o.vnew ? 1 : 0;
         wave_append(o.gnew, o.g, A.gwl, &A.ctl->gtail, true);
       } else {
-        if (w[j] >= 0) mark_vertex_sync(A.flags, w[j]);
+        if (w[j] >= 0 && mark_vertex_sync(A.flags, w[j])) ++newly;
       }
     }
   }
@@ -301,10 +302,17 @@ __device__ __forceinline__ void finish_rows(const RankArgs<T> &A, WaveLds<T> &L,
         // left to mark: affected flags are never cleared within an update
         if (!(flag_byte(A.flags, x, COH) & kEX)) {
           expand[k] = true;
-          od[k] = d;
-          oo[k] = A.out_off[x];
           cnt.out_scanned += (unsigned long long)d;
-          any_expand = any_expand || d > 0;
+          if (MODE == kSyncDF && d >= A.split_min) {
+            // marked after the iteration by whole workgroups (the marks
+            // take effect in the next iteration either way)
+            const unsigned long long j = atomicAdd(&A.ctl->nexp, 1ull);
+            A.xrow[j] = x;
+          } else {
+            od[k] = d;
+            oo[k] = A.out_off[x];
+            any_expand = any_expand || d > 0;
+          }
         }
       }
     }
@@ -655,6 +663,7 @@ __global__ void __launch_bounds__(256) k_sync_iter(RankArgs<T> A, int iter,
   const int lane = lane_id();
   Counters cnt;
   double maxdr = 0.0;
+  long long newly = 0;  // vertices this wavefront marked for the first time
   // pieces of long rows first (their finishing wavefronts may still have
   // an out-row to mark), then the steps
   const unsigned long long packed = A.sync_len[iter];
@@ -672,8 +681,7 @@ __global__ void __launch_bounds__(256) k_sync_iter(RankArgs<T> A, int iter,
     if (u >= nitems) break;
     if (u < npieces) {
       bool unused_moved = false;
-      long long unused_newly = 0;
-      process_piece<T, MODE>(A, L, (int32_t)u, cnt, maxdr, unused_newly, unused_moved);
+      process_piece<T, MODE>(A, L, (int32_t)u, cnt, maxdr, newly, unused_moved);
       continue;
     }
     u -= npieces;
@@ -685,13 +693,37 @@ __global__ void __launch_bounds__(256) k_sync_iter(RankArgs<T> A, int iter,
       vv[k] = pos < end ? (MODE == kAll ? pos : A.wl[pos]) : -1;
     }
     bool unused_moved = false;
-    long long unused_newly = 0;
-    process_step<T, MODE>(A, L, vv, cnt, maxdr, unused_newly, unused_moved);
+    process_step<T, MODE>(A, L, vv, cnt, maxdr, newly, unused_moved);
   }
   maxdr = wave_max(maxdr);
   if (lane == 0 && maxdr > 0.0)
     atomicMax(&A.sync_max[iter], (unsigned long long)__double_as_longlong(maxdr));
   flush_counters<T>(A.ctl, cnt);
+  newly = wave_sum(newly);
+  if (lane == 0 && newly)
+    atomicAdd((unsigned long long *)&A.ctl->newly, (unsigned long long)newly);
+}
+
+// Marks the out-neighbours of the long out-rows deferred by the iteration
+// (one workgroup per row, threads striding it) and counts the newly
+// affected vertices.
+__global__ void __launch_bounds__(256) k_expand_long(const int32_t *xrow,
+                                                     const int64_t *out_off,
+                                                     const int32_t *out_deg,
+                                                     const int32_t *out_adj,
+                                                     uint32_t *flags, Ctl *ctl) {
+  const unsigned long long nx = ctl->nexp;
+  long long newly = 0;
+  for (unsigned long long j = blockIdx.x; j < nx; j += gridDim.x) {
+    const int32_t v = xrow[j];
+    const int32_t *row = out_adj + out_off[v];
+    const int32_t d = out_deg[v];
+    for (int32_t e = threadIdx.x; e < d; e += blockDim.x)
+      if (mark_vertex_sync(flags, row[e])) ++newly;
+  }
+  newly = wave_sum(newly);
+  if (lane_id() == 0 && newly)
+    atomicAdd((unsigned long long *)&ctl->newly, (unsigned long long)newly);
 }
 
 __global__ void k_sync_finish(Ctl *ctl, const unsigned long long *sync_max,
@@ -699,6 +731,10 @@ __global__ void k_sync_finish(Ctl *ctl, const unsigned long long *sync_max,
                               unsigned long long *claims, int iter,
                               double tol, int max_iters, int df) {
   if (threadIdx.x < kClaimers) claims[threadIdx.x * kClaimStride] = 0;
+  if (threadIdx.x == 0) {
+    ctl->newly = 0;
+    ctl->nexp = 0;
+  }
   if (threadIdx.x != 0 || ctl->sync_done) return;
   const double md = __longlong_as_double((long long)sync_max[iter]);
   if (md <= tol || iter + 1 >= max_iters) {
@@ -726,6 +762,8 @@ __global__ void k_sync_begin(Ctl *ctl, unsigned long long *sync_max,
     ctl->sync_conv = 0;
     ctl->vertices = ctl->edges = ctl->out_scanned = 0;
     ctl->abort = 0;
+    ctl->newly = 0;
+    ctl->nexp = 0;
   }
 }
 
@@ -979,6 +1017,7 @@ RankArgs<T> make_args(dfpr_graph *g, int rd, int wr) {
   A.prow = g->split.prow;
   A.ppart = g->split.ppart;
   A.lcnt = g->split.lcnt;
+  A.xrow = g->split.xrow;
   return A;
 }
 
@@ -1095,7 +1134,9 @@ __device__ __forceinline__ TileScan tile_scan(const uint8_t *flags,
 template <bool ALL>
 __global__ void __launch_bounds__(256) k_tile_count(const uint8_t *flags,
                                                     const int32_t *deg, int32_t n,
-                                                    int32_t split, TileSum *sums) {
+                                                    int32_t split, TileSum *sums,
+                                                    const Ctl *ctl, int reuse) {
+  if (reuse && ctl->newly == 0) return;  // nothing newly affected: keep
   const TileScan r = tile_scan<ALL>(flags, deg, n, split);
   if (threadIdx.x == 0) {
     sums[blockIdx.x] = r.tot;
@@ -1108,7 +1149,8 @@ __global__ void __launch_bounds__(256) k_tile_emit(const uint8_t *flags,
                                                    const int32_t *deg, int32_t n,
                                                    int32_t split, const TileSum *pre,
                                                    int32_t *wl, int32_t *steps,
-                                                   Split S, Ctl *ctl) {
+                                                   Split S, Ctl *ctl, int reuse) {
+  if (reuse && ctl->newly == 0) return;
   const TileScan r = tile_scan<ALL>(flags, deg, n, split);
   const TileSum b = pre[blockIdx.x];
   if (r.sel) {
@@ -1134,18 +1176,21 @@ __global__ void __launch_bounds__(256) k_tile_emit(const uint8_t *flags,
   }
 }
 
-// Sizes the piece arrays for the current adjacency capacity and threshold:
-// a row with at least split_min in-edges holds that many slots, so at most
-// adj_cap / split_min rows are long, and they have at most
-// adj_cap / kPiece + (long rows) pieces.
+// Sizes the piece arrays for the current adjacency capacities and
+// threshold: a row with at least split_min entries holds that many slots,
+// so at most adj_cap / split_min in-rows are long (with at most
+// adj_cap / kPiece + (long rows) pieces), and at most out adj_cap /
+// split_min out-rows can be deferred in one iteration.
 int ensure_split(dfpr_graph *g) {
   Split &S = g->split;
   int64_t lcap = g->in.adj_cap / g->p.split_min_degree + 1;
   if (lcap > (int64_t)g->n + 1) lcap = (int64_t)g->n + 1;
   const int64_t pcap = g->in.adj_cap / kPiece + lcap + 1;
-  if (lcap <= S.lcap && pcap <= S.pcap) return DFPR_OK;
+  int64_t xcap = g->out.adj_cap / g->p.split_min_degree + 1;
+  if (xcap > (int64_t)g->n + 1) xcap = (int64_t)g->n + 1;
+  if (lcap <= S.lcap && pcap <= S.pcap && xcap <= S.xcap) return DFPR_OK;
   DFPR_HIP(hipStreamSynchronize(g->stream));
-  void *old[] = {S.lrow, S.lpre, S.lcnt, S.prow, S.ppart};
+  void *old[] = {S.lrow, S.lpre, S.lcnt, S.prow, S.ppart, S.xrow};
   for (void *p : old)
     if (p) DFPR_HIP(hipFree(p));
   S = Split();
@@ -1154,15 +1199,18 @@ int ensure_split(dfpr_graph *g) {
   DFPR_HIP(hipMalloc(&S.lcnt, (size_t)lcap * 4));
   DFPR_HIP(hipMalloc(&S.prow, (size_t)pcap * 4));
   DFPR_HIP(hipMalloc(&S.ppart, (size_t)pcap * 8));
+  DFPR_HIP(hipMalloc(&S.xrow, (size_t)xcap * 4));
   DFPR_HIP(hipMemsetAsync(S.lcnt, 0, (size_t)lcap * 4, g->stream));
   S.lcap = lcap;
   S.pcap = pcap;
+  S.xcap = xcap;
   return DFPR_OK;
 }
 
 // Builds the work items of the next barrier-based iteration (all = true:
-// every vertex, static PageRank).
-int build_items(dfpr_graph *g, bool all) {
+// every vertex, static PageRank).  reuse: the previous items stay when the
+// last iteration affected no new vertex (decided on the device).
+int build_items(dfpr_graph *g, bool all, bool reuse) {
   hipStream_t s = g->stream;
   if (g->n == 0) {
     DFPR_HIP(hipMemsetAsync(&g->ctl->tail, 0, 4 * sizeof(unsigned long long), s));
@@ -1178,9 +1226,10 @@ int build_items(dfpr_graph *g, bool all) {
   const uint8_t *fl = reinterpret_cast<const uint8_t *>(g->flags);
   const int32_t split = g->p.split_min_degree;
   if (all)
-    k_tile_count<true><<<nt, 256, 0, s>>>(fl, g->in.deg, g->n, split, sums);
+    k_tile_count<true><<<nt, 256, 0, s>>>(fl, g->in.deg, g->n, split, sums, g->ctl, 0);
   else
-    k_tile_count<false><<<nt, 256, 0, s>>>(fl, g->in.deg, g->n, split, sums);
+    k_tile_count<false><<<nt, 256, 0, s>>>(fl, g->in.deg, g->n, split, sums, g->ctl,
+                                           reuse);
   DFPR_HIP(hipGetLastError());
   size_t tb = 0;
   const TileSum zero{0, 0, 0, 0};
@@ -1192,10 +1241,10 @@ int build_items(dfpr_graph *g, bool all) {
                                    TileSumPlus(), s));
   if (all)
     k_tile_emit<true><<<nt, 256, 0, s>>>(fl, g->in.deg, g->n, split, pre, g->wl, g->steps,
-                                         g->split, g->ctl);
+                                         g->split, g->ctl, 0);
   else
     k_tile_emit<false><<<nt, 256, 0, s>>>(fl, g->in.deg, g->n, split, pre, g->wl, g->steps,
-                                          g->split, g->ctl);
+                                          g->split, g->ctl, reuse);
   DFPR_HIP(hipGetLastError());
   return DFPR_OK;
 }
@@ -1214,12 +1263,13 @@ int run_sync(dfpr_graph *g, int mode, dfpr_stats *st) {
   {
     int rc = ensure_split(g);
     if (rc) return rc;
-    if ((rc = build_items(g, mode == kAll))) return rc;
+    if ((rc = build_items(g, mode == kAll, false))) return rc;
   }
   k_sync_begin<<<4, 256, 0, s>>>(g->ctl, g->sync_max, g->sync_grab, g->sync_len, iters);
   DFPR_HIP(hipGetLastError());
   auto kern = mode == kAll ? k_sync_iter<T, kAll> : k_sync_iter<T, kSyncDF>;
   const int blocks = persistent_blocks(g, kern);
+  const int xgrid = g->cu_count > 0 ? g->cu_count : 1;
   DFPR_HIP(hipEventRecord(g->ev[1], s));
   const int poll = 8;
   int it = 0;
@@ -1227,7 +1277,9 @@ int run_sync(dfpr_graph *g, int mode, dfpr_stats *st) {
     RankArgs<T> A = make_args<T>(g, (g->cur + it) & 1, (g->cur + it + 1) & 1);
     kern<<<blocks, g->p.block_size, 0, s>>>(A, it, g->steps);
     if (mode != kAll) {
-      int rc = build_items(g, false);
+      k_expand_long<<<xgrid, 256, 0, s>>>(g->split.xrow, g->out.off, g->out.deg,
+                                          g->out.adj, g->flags, g->ctl);
+      int rc = build_items(g, false, true);
       if (rc) return rc;
     }
     k_sync_finish<<<1, 64, 0, s>>>(g->ctl, g->sync_max, g->sync_len, g->sync_grab, it,
