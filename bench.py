@@ -95,8 +95,11 @@ def batch_seed(name, frac):
 
 
 def kernel_sha():
-    src = os.path.join(ROOT, "paper_2407_19562_amd", "csrc", "dfpr_rank.hip")
-    return hashlib.sha1(open(src, "rb").read()).hexdigest()[:12]
+    """Hash of the rank kernels' sources (dfpr_rank.hip, then dfpr_common.h)."""
+    h = hashlib.sha1()
+    for f in ("dfpr_rank.hip", "dfpr_common.h"):
+        h.update(open(os.path.join(ROOT, "paper_2407_19562_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:12]
 
 
 def traffic_record(tag):

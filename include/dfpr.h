@@ -92,7 +92,8 @@ typedef struct {
   int32_t chunk;         /* lock-free scheme: worklist groups per dynamic
                             grab are chunk / 256 (at least one); a multiple
                             of 64 in [64, 4096]                             */
-  int32_t block_size;    /* threads per workgroup (64, 128, 192 or 256)     */
+  int32_t block_size;    /* threads per workgroup: 64, 128 (default), 192 or
+                            256                                             */
   int32_t reorder;       /* internal vertex order, fixed at creation:
                             0 keep the caller's ids; 1 sort by decreasing
                             out-degree, so the contributions read most often
@@ -119,7 +120,9 @@ typedef struct {
   double max_delta;      /* sync: L-infinity change of the last iteration;
                             async: -1 (not tracked)                         */
   float ms;              /* device time of the call (HIP events)            */
-  float ms_kernel;       /* device time of the rank iteration alone         */
+  float ms_kernel;       /* device time of the rank kernel launches alone
+                            (barrier-based: sum over the iteration kernels,
+                            without the item building between them)        */
 } dfpr_stats;
 
 /* Fills `p` with the paper's defaults (alpha 0.85, tol 1e-10,

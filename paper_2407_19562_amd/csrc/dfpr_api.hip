@@ -88,6 +88,8 @@ static void release(dfpr_graph *g) {
   if (g->h_ctl) (void)hipHostFree(g->h_ctl);
   for (auto &e : g->ev)
     if (e) (void)hipEventDestroy(e);
+  for (auto &e : g->iter_ev)
+    if (e) (void)hipEventDestroy(e);
   delete g;
 }
 
@@ -165,7 +167,7 @@ int dfpr_params_default(dfpr_params *p) {
   p->kahan_min_degree = 64;
   p->split_min_degree = 2048;
   p->chunk = 256;
-  p->block_size = 256;
+  p->block_size = 128;
   p->reorder = 2;
   p->renormalize = 0;
   p->timeout_ms = 60000;

@@ -22,6 +22,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/dfpr.h"
 
@@ -154,6 +155,8 @@ struct dfpr_graph {
   int64_t pending_marks = 0;  // host view of marks not yet consumed
   dfpr::Scratch scratch[16];
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  std::vector<hipEvent_t> iter_ev;  // around each barrier-based iteration
+                                    // kernel: [2 * i] before, [2 * i + 1] after
   double last_bytes = 0.0;
   int32_t last_launches = 0;
   int cu_count = 0;

@@ -1270,12 +1270,19 @@ int run_sync(dfpr_graph *g, int mode, dfpr_stats *st) {
   auto kern = mode == kAll ? k_sync_iter<T, kAll> : k_sync_iter<T, kSyncDF>;
   const int blocks = persistent_blocks(g, kern);
   const int xgrid = g->cu_count > 0 ? g->cu_count : 1;
+  while ((int)g->iter_ev.size() < 2 * iters) {
+    hipEvent_t e = nullptr;
+    DFPR_HIP(hipEventCreate(&e));
+    g->iter_ev.push_back(e);
+  }
   DFPR_HIP(hipEventRecord(g->ev[1], s));
   const int poll = 8;
   int it = 0;
   for (; it < iters; ++it) {
     RankArgs<T> A = make_args<T>(g, (g->cur + it) & 1, (g->cur + it + 1) & 1);
+    DFPR_HIP(hipEventRecord(g->iter_ev[2 * it], s));
     kern<<<blocks, g->p.block_size, 0, s>>>(A, it, g->steps);
+    DFPR_HIP(hipEventRecord(g->iter_ev[2 * it + 1], s));
     if (mode != kAll) {
       k_expand_long<<<xgrid, 256, 0, s>>>(g->split.xrow, g->out.off, g->out.deg,
                                           g->out.adj, g->flags, g->ctl);
@@ -1312,8 +1319,14 @@ int run_sync(dfpr_graph *g, int mode, dfpr_stats *st) {
     st->edges_gathered = (int64_t)h.edges;
     st->out_edges_scanned = (int64_t)h.out_scanned;
     st->max_delta = md;
+    // the iteration kernels alone (the item building between them is not
+    // included); iterations after the last one exit at once
     float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, g->ev[1], g->ev[2]);
+    for (int i = 0; i < final_it; ++i) {
+      float x = 0.f;
+      (void)hipEventElapsedTime(&x, g->iter_ev[2 * i], g->iter_ev[2 * i + 1]);
+      ms += x;
+    }
     st->ms_kernel = ms;
   }
   return h.sync_conv ? DFPR_OK : DFPR_NOTCONVERGED;
