@@ -19,6 +19,10 @@
 // current out-neighbours and the targets of its deleted edges -- together
 // (G^{t-1} union G^t).out(u) -- get the affected and not-converged flags,
 // and newly affected vertices are appended to the worklist.
+// Rows of at least kLongApply entries are not left to one wavefront:
+// their deletions run in a second launch with a 1024-thread workgroup per
+// row (segment keys staged in LDS, block-wide compaction), and their
+// out-rows are marked by every wavefront of a second launch together.
 #include <cstring>
 
 #include <rocprim/device/device_radix_sort.hpp>
@@ -32,6 +36,10 @@ namespace {
 
 constexpr unsigned long long kNoKey = ~0ull;
 constexpr uint8_t kApplied = 1, kExists = 2;
+constexpr int32_t kLongApply = 4096;  // row entries from which rows are
+                                      // edited by more than one wavefront
+constexpr int kLongBlock = 1024;      // threads of a long-row deletion block
+constexpr int kKeyLds = 2048;         // segment keys staged in LDS
 
 inline int grid_for(int64_t work, int cu) {
   int64_t b = (work + 255) / 256;
@@ -129,7 +137,8 @@ struct AdjView {
 
 __global__ void k_apply_delete(int64_t S, const int64_t *segstart,
                                const unsigned long long *uk, uint8_t *status,
-                               AdjView A) {
+                               AdjView A, int32_t *long_list,
+                               unsigned long long *long_cnt) {
   const int lane = lane_id();
   const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -144,6 +153,10 @@ __global__ void k_apply_delete(int64_t S, const int64_t *segstart,
     const uint32_t row = (uint32_t)(uk[a] >> 32);
     const int64_t off = A.off[row];
     const int32_t deg = A.deg[row];
+    if (deg >= kLongApply) {  // k_apply_delete_long
+      if (lane == 0) long_list[atomicAdd(long_cnt, 1ull)] = (int32_t)s;
+      continue;
+    }
     int32_t w = 0;
     for (int32_t t = 0; t < deg; t += kWave) {
       const int32_t idx = t + lane;
@@ -162,6 +175,99 @@ __global__ void k_apply_delete(int64_t S, const int64_t *segstart,
       w += __popcll(mask);
     }
     if (lane == 0) A.deg[row] = w;
+  }
+}
+
+// Lookup of `key` among n sorted keys in LDS; index or -1.
+__device__ __forceinline__ int32_t find_key_lds(const unsigned long long *keys,
+                                                int32_t n, unsigned long long key) {
+  int32_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (keys[mid] < key)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return (lo < n && keys[lo] == key) ? lo : -1;
+}
+
+// Exclusive prefix of x over the workgroup (at most 1024 threads, whole
+// wavefronts); *total = sum.  Starts with a barrier, so the LDS it uses can
+// be reused by the next call.
+__device__ __forceinline__ int32_t block_scan_excl(int32_t x, int32_t *lds,
+                                                   int32_t *total) {
+  const int lane = lane_id();
+  const int w = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+  int32_t incl = x;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int32_t y = __shfl_up(incl, o);
+    if (lane >= o) incl += y;
+  }
+  __syncthreads();
+  if (lane == kWave - 1) lds[w] = incl;
+  __syncthreads();
+  int32_t before = 0, sum = 0;
+  for (int i = 0; i < nw; ++i) {
+    const int32_t t = lds[i];
+    before += i < w ? t : 0;
+    sum += t;
+  }
+  *total = sum;
+  return before + incl - x;
+}
+
+// Deletions on the rows k_apply_delete deferred: one workgroup per row,
+// row entries looked up among the segment's keys (staged in LDS when they
+// fit) and the survivors compacted in place in order.
+__global__ void __launch_bounds__(kLongBlock) k_apply_delete_long(
+    const int32_t *long_list, const unsigned long long *long_cnt,
+    const int64_t *segstart, const unsigned long long *uk, uint8_t *status,
+    AdjView A) {
+  __shared__ unsigned long long keys[kKeyLds];
+  __shared__ int32_t part[kLongBlock / kWave];
+  const unsigned long long cnt = *long_cnt;
+  for (unsigned long long j = blockIdx.x; j < cnt; j += gridDim.x) {
+    const int64_t sg = long_list[j];
+    const int64_t a = segstart[sg], b = segstart[sg + 1];
+    const int64_t nk = b - a;
+    const bool staged = nk <= kKeyLds;
+    __syncthreads();  // the previous row's readers of `keys` are done
+    if (staged)
+      for (int64_t i = threadIdx.x; i < nk; i += blockDim.x) keys[i] = uk[a + i];
+    __syncthreads();
+    const uint32_t row = (uint32_t)(uk[a] >> 32);
+    const int64_t off = A.off[row];
+    const int32_t deg = A.deg[row];
+    int32_t w = 0;
+    for (int32_t t = 0; t < deg; t += blockDim.x) {
+      const int32_t idx = t + (int32_t)threadIdx.x;
+      int32_t x = -1;
+      bool keep = false;
+      if (idx < deg) {
+        x = A.adj[off + idx];
+        const unsigned long long key =
+            (unsigned long long)row << 32 | (unsigned long long)(uint32_t)x << 1;
+        int64_t k = -1;
+        if (staged) {
+          const int32_t q = find_key_lds(keys, (int32_t)nk, key);
+          k = q >= 0 ? a + q : -1;
+        } else {
+          k = find_key(uk, a, b, key);
+        }
+        if (k >= 0) status[k] |= kApplied;
+        keep = k < 0;
+      }
+      int32_t total = 0;
+      // every entry of this round is read before the scan's barriers; the
+      // survivors land at or below their own positions
+      const int32_t pos = block_scan_excl(keep ? 1 : 0, part, &total);
+      if (keep) A.adj[off + w + pos] = x;
+      w += total;
+    }
+    if (threadIdx.x == 0) A.deg[row] = w;
   }
 }
 
@@ -275,7 +381,7 @@ __global__ void k_mark_sources(int64_t S, const int64_t *segstart,
                                const uint8_t *status, AdjView out,
                                const T *R, T *C, uint32_t *flags,
                                uint32_t *gflags, int32_t *wl, int32_t *gwl,
-                               Ctl *ctl) {
+                               Ctl *ctl, int32_t *long_list) {
   const int lane = lane_id();
   const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -296,10 +402,14 @@ __global__ void k_mark_sources(int64_t S, const int64_t *segstart,
     const int64_t off = out.off[u];
     const int32_t deg = out.deg[u];
     if (lane == 0) C[u] = (T)((double)R[u] / (double)(deg + 1));
-    // u itself (implicit self-loop), then its current out-row
-    for (int32_t t = -1; t < deg; t += kWave) {
+    // u itself (implicit self-loop), then its current out-row (long rows:
+    // k_mark_long)
+    const bool defer = deg >= kLongApply;
+    if (defer && lane == 0) long_list[atomicAdd(&ctl->nlong_mark, 1ull)] = u;
+    const int32_t rdeg = defer ? 0 : deg;
+    for (int32_t t = -1; t < rdeg; t += kWave) {
       const int32_t idx = t + lane;
-      const bool act = idx < deg;
+      const bool act = idx < rdeg;
       mark(act, act ? (idx < 0 ? u : out.adj[off + idx]) : -1);
     }
     // targets of the deleted edges of u (they were out-neighbours in G^{t-1})
@@ -307,6 +417,33 @@ __global__ void k_mark_sources(int64_t S, const int64_t *segstart,
       const int64_t e = i + lane;
       const bool act = e < b && !(uk[e] & 1ull) && (status[e] & kApplied);
       mark(act, act ? (int32_t)((uk[e] >> 1) & 0x7FFFFFFFull) : -1);
+    }
+  }
+  if (lane == 0 && appended)
+    atomicAdd((unsigned long long *)&ctl->marked, (unsigned long long)appended);
+}
+
+// Out-rows deferred by k_mark_sources: every wavefront of the launch takes
+// its share of 64-entry chunks of every such row.
+__global__ void k_mark_long(const int32_t *long_list, AdjView out, uint32_t *flags,
+                            uint32_t *gflags, int32_t *wl, int32_t *gwl, Ctl *ctl) {
+  const int lane = lane_id();
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const unsigned long long cnt = ctl->nlong_mark;
+  long long appended = 0;
+  for (unsigned long long j = 0; j < cnt; ++j) {
+    const int32_t u = long_list[j];
+    const int64_t off = out.off[u];
+    const int32_t deg = out.deg[u];
+    for (int64_t base = wave * kWave; base < deg; base += nwaves * kWave) {
+      const int64_t idx = base + lane;
+      const bool act = idx < deg;
+      MarkOut o{false, false, -1};
+      const int32_t v = act ? out.adj[off + idx] : -1;
+      if (act) o = mark_affected(flags, gflags, v);
+      appended += wave_append(o.vnew, v, wl, &ctl->tail, true);
+      wave_append(o.gnew, o.g, gwl, &ctl->gtail, true);
     }
   }
   if (lane == 0 && appended)
@@ -422,7 +559,9 @@ int apply_batch(dfpr_graph *g, int64_t nd, const int32_t *ds,
   int64_t *seg[2];
   uint8_t *st[2];
   int64_t U[2], S[2];
-  // in direction first (slots 4..6 are reused by the out direction's marks)
+  // in direction first; slot 14 holds each direction's list of long rows
+  // with deletions in turn, slot 0 (free once both directions are
+  // prepared) the marking's list of long out-rows
   for (int dir = 1; dir >= 0; --dir) {
     const int base = 8 + 3 * dir;
     int rc = prepare_direction(g, dir, nd, ds, dd, ni, is, id, base, &uk[dir],
@@ -433,7 +572,15 @@ int apply_batch(dfpr_graph *g, int64_t nd, const int32_t *ds,
     uint8_t *done = st[dir] + (U[dir] > 0 ? U[dir] : 1);
     const int blocks = grid_for(S[dir] * 64, cu);
     AdjView v{A.off, A.deg, A.cap, A.adj, A.adj_cap};
-    k_apply_delete<<<blocks, 256, 0, s>>>(S[dir], seg[dir], uk[dir], st[dir], v);
+    void *ll = nullptr;
+    int rc1 = scratch_get(g, 14, (size_t)S[dir] * 4, &ll);
+    if (rc1) return rc1;
+    DFPR_HIP(hipMemsetAsync(&g->ctl->nlong_del, 0, sizeof(unsigned long long), s));
+    k_apply_delete<<<blocks, 256, 0, s>>>(S[dir], seg[dir], uk[dir], st[dir], v,
+                                          (int32_t *)ll, &g->ctl->nlong_del);
+    DFPR_HIP(hipGetLastError());
+    k_apply_delete_long<<<cu > 0 ? cu : 1, kLongBlock, 0, s>>>(
+        (const int32_t *)ll, &g->ctl->nlong_del, seg[dir], uk[dir], st[dir], v);
     DFPR_HIP(hipGetLastError());
     for (int attempt = 0; attempt < 16; ++attempt) {
       AdjView w{A.off, A.deg, A.cap, A.adj, A.adj_cap};
@@ -460,14 +607,23 @@ int apply_batch(dfpr_graph *g, int64_t nd, const int32_t *ds,
   if (S[0] > 0) {
     const int blocks = grid_for(S[0] * 64, cu);
     AdjView o{g->out.off, g->out.deg, g->out.cap, g->out.adj, g->out.adj_cap};
+    void *ml = nullptr;
+    int rc1 = scratch_get(g, 0, (size_t)S[0] * 4, &ml);
+    if (rc1) return rc1;
+    DFPR_HIP(hipMemsetAsync(&g->ctl->nlong_mark, 0, sizeof(unsigned long long), s));
     if (g->elem == 8)
       k_mark_sources<double><<<blocks, 256, 0, s>>>(
           S[0], seg[0], uk[0], st[0], o, (const double *)g->R[g->cur],
-          (double *)g->C[g->cur], g->flags, g->gflags, g->wl, g->gwl, g->ctl);
+          (double *)g->C[g->cur], g->flags, g->gflags, g->wl, g->gwl, g->ctl,
+          (int32_t *)ml);
     else
       k_mark_sources<float><<<blocks, 256, 0, s>>>(
           S[0], seg[0], uk[0], st[0], o, (const float *)g->R[g->cur],
-          (float *)g->C[g->cur], g->flags, g->gflags, g->wl, g->gwl, g->ctl);
+          (float *)g->C[g->cur], g->flags, g->gflags, g->wl, g->gwl, g->ctl,
+          (int32_t *)ml);
+    DFPR_HIP(hipGetLastError());
+    k_mark_long<<<cu > 0 ? 4 * cu : 1, 256, 0, s>>>((const int32_t *)ml, o, g->flags,
+                                                   g->gflags, g->wl, g->gwl, g->ctl);
     DFPR_HIP(hipGetLastError());
   }
   DFPR_HIP(hipMemcpyAsync(g->h_ctl, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));

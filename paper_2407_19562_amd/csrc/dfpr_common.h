@@ -68,6 +68,8 @@ struct Ctl {
   unsigned long long nlong;               // rows gathered in pieces
   unsigned long long npieces;             // their pieces
   unsigned long long nexp;                // long out-rows left to mark
+  unsigned long long nlong_del;           // apply: long rows with deletions
+  unsigned long long nlong_mark;          // apply: long out-rows to mark
   alignas(128) unsigned long long gtail;  // group worklist length
   alignas(128) long long change_sweep;    // last sweep in which a claim saw a
                                           // change above the frontier tol
@@ -117,7 +119,14 @@ struct Split {
   int64_t lcap = 0, pcap = 0, xcap = 0;
 };
 
-// Reusable device scratch of apply_batch (grown on demand).
+// Reusable device scratch (grown on demand), in 16 slots:
+//   graph build   0-7 temporaries; 14, 15 staged host edge arrays
+//   apply_batch   4, 5, 6, 15 staged host batch arrays; per direction 0-3
+//                 and 7 temporaries, 8-10 (out) / 11-13 (in) sorted keys,
+//                 segments and status; 14 long rows with deletions; 0 long
+//                 out-rows to mark (after both directions are prepared)
+//   update        14 scan temporaries, 15 tile sums; update_many 12
+//                 descriptors; 13 rank staging of set/read calls
 struct Scratch {
   void *p = nullptr;
   size_t bytes = 0;

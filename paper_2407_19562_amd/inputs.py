@@ -266,19 +266,27 @@ def road_grid(seed: int = 3, side: int = 4096):
 
 
 def heavy_rows(seed: int = 5, n: int = 30000, avg_degree: int = 4,
-               hub_in=(4095, 4096, 4097, 8192, 12289, 25000)):
-    """G(n, m) with average degree `avg_degree`, plus hubs 0..len(hub_in)-1
-    whose in-degrees are exactly the listed values (edges from distinct
-    random sources) (rows just below, at and above the 4096-edge piece size
-    and several pieces long).  Returns (n, src, dst) without duplicates."""
+               hub_in=(4095, 4096, 4097, 8192, 12289, 25000),
+               hub_out=(4096, 9000, 20000)):
+    """G(n, m) with average degree `avg_degree`, plus in-hubs
+    0..len(hub_in)-1 whose in-degrees are exactly the listed values (edges
+    from distinct random sources; rows just below, at and above 4096 and
+    several times that) and out-hubs numbered after them whose out-degrees
+    are exactly `hub_out`.  Returns (n, src, dst) without duplicates."""
     rng = np.random.default_rng(seed)
     n0, s0, d0 = erdos_renyi(n, n * avg_degree, seed)
-    keep = d0 >= len(hub_in)             # hubs get only the edges below
+    h_in = len(hub_in)
+    outs = np.arange(h_in, h_in + len(hub_out))
+    keep = (d0 >= h_in) & ~np.isin(s0, outs)   # hubs get only the edges below
     keys = [s0[keep].astype(np.int64) * n + d0[keep]]
     for h, k in enumerate(hub_in):
-        src = rng.choice(n, size=k + 1, replace=False)
-        src = src[src != h][:k]
+        src = rng.choice(n, size=k + 1 + len(outs), replace=False)
+        src = src[(src != h) & ~np.isin(src, outs)][:k]
         keys.append(src.astype(np.int64) * n + h)
+    for h, k in zip(outs, hub_out):
+        dst = rng.choice(np.arange(h_in, n), size=k + 1, replace=False)
+        dst = dst[dst != h][:k]
+        keys.append(np.int64(h) * n + dst.astype(np.int64))
     keys = np.unique(np.concatenate(keys))
     keys = rng.permutation(keys)
     return n, (keys // n).astype(np.int32), (keys % n).astype(np.int32)

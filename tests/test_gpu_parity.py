@@ -99,10 +99,11 @@ def test_apply_set_semantics(D, O):
                                   edge_keys(n, ns, nd))
 
 
-@pytest.mark.parametrize("frac", [1e-3, 5e-2, 0.3])
-def test_apply_batches_match_oracle(D, O, frac):
-    say("apply batches", frac)
-    n, s, d = inputs.rmat_small()
+@pytest.mark.parametrize("kind,frac", [("rmat_small", 1e-3), ("rmat_small", 5e-2),
+                                       ("rmat_small", 0.3), ("heavy_rows", 5e-2)])
+def test_apply_batches_match_oracle(D, O, kind, frac):
+    say("apply batches", kind, frac)
+    n, s, d = getattr(inputs, kind)()
     bs = inputs.batches(n, s, d, 3, seed=31, frac=frac)
     cs, cd = s, d
     with graph(D, n, s, d) as g:
@@ -134,6 +135,42 @@ def test_apply_row_relocation_and_growth(D, O):
                                   edge_keys(n, ns, nd))
 
 
+def test_apply_long_rows(D, O):
+    # rows of 4096+ entries are edited by whole workgroups: 3000 deletions
+    # in one out-row (more keys than fit in LDS), 900 in one in-row, plus
+    # insertions on the same rows; edge sets, counts and marks must match
+    say("apply long rows")
+    n, s, d = inputs.heavy_rows()
+    rng = np.random.default_rng(12)
+    hub_out, hub_in = 8, 5                 # out-degree 20000, in-degree 25000
+    eo = np.flatnonzero(s == hub_out)
+    ei = np.flatnonzero(d == hub_in)
+    dsel = np.concatenate([rng.choice(eo, 3000, replace=False),
+                           rng.choice(ei, 900, replace=False)])
+    dsel = np.unique(dsel)
+    keyset = set((s.astype(np.int64) * n + d).tolist())
+    ins = []
+    while len(ins) < 400:
+        a, b = (hub_out, int(rng.integers(0, n))) if len(ins) % 2 else (int(rng.integers(0, n)), hub_in)
+        if a != b and a * n + b not in keyset:
+            keyset.add(a * n + b)
+            ins.append((a, b))
+    is_, id_ = (np.array(x, np.int32) for x in zip(*ins))
+    ns, nd, dt, it = O.apply_batch(n, s, d, s[dsel], d[dsel], is_, id_)
+    R, _, _ = O.pagerank(n, s, d)
+    src = np.concatenate([dt // n, it // n]).astype(np.int32)
+    ref = O.df_bb(n, (s, d), (ns, nd), src, R, max_iters=0)
+    with graph(D, n, s, d) as g:
+        ad, ai = g.apply_batch(s[dsel], d[dsel], is_, id_)
+        assert (ad, ai) == (dt.size, it.size)
+        for direction in (D.DFPR_OUT, D.DFPR_IN):
+            assert np.array_equal(edge_keys(n, *g.edges(direction)),
+                                  edge_keys(n, ns, nd))
+        aff, cnt = g.marks()
+        assert np.array_equal(aff, ref.affected)
+        assert cnt == ref.initial_marked
+
+
 def test_invalid_batch_is_rejected_whole(D, O):
     say("invalid batch")
     n, s, d = inputs.rmat(8, 1000, seed=3)
@@ -163,11 +200,12 @@ def test_marking_frontier_example(D, O):
         assert cnt == 5
 
 
-@pytest.mark.parametrize("reorder", [0, 1])
-def test_marking_matches_oracle_rmat(D, O, reorder):
-    say("marking rmat", reorder)
-    n, s, d = inputs.rmat_small()
-    b = inputs.batches(n, s, d, 1, 1001, frac=1e-3)[0]
+@pytest.mark.parametrize("kind,reorder", [("rmat_small", 0), ("rmat_small", 1),
+                                          ("heavy_rows", 0)])
+def test_marking_matches_oracle_rmat(D, O, kind, reorder):
+    say("marking", kind, reorder)
+    n, s, d = getattr(inputs, kind)()
+    b = inputs.batches(n, s, d, 1, 1001, frac=1e-2 if kind == "heavy_rows" else 1e-3)[0]
     R, _, _ = O.pagerank(n, s, d)
     ns, nd, dt, it = O.apply_batch(n, s, d, b.del_src, b.del_dst, b.ins_src, b.ins_dst)
     src = np.concatenate([dt // n, it // n]).astype(np.int32)
