@@ -105,7 +105,11 @@ typedef struct {
   int32_t renormalize;   /* fp32: rescale ranks to sum 1 (fp64 sum) after
                             each update                                     */
   int32_t timeout_ms;    /* watchdog for the persistent kernel (0: none)    */
-  int32_t grid_blocks;   /* persistent grid size; 0 = from occupancy        */
+  int32_t grid_blocks;   /* workgroups of the rank kernels; 0 = automatic:
+                            barrier-based, at most 14 wavefronts per CU and
+                            no more than an iteration's work items;
+                            lock-free, the co-resident workgroups, at most
+                            one wavefront per listed vertex group          */
 } dfpr_params;
 
 typedef struct {

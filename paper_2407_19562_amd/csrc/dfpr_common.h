@@ -53,11 +53,20 @@ constexpr int kCursorShift = 16;
 constexpr uint64_t kCursorMask = 0xFFFFFFFFull;
 constexpr uint64_t kInflightMask = 0xFFFFull;
 
-// Claim counters of the barrier-based iteration (unsigned long long, 128
-// bytes apart); wavefront w claims the items c + kClaimers * k from counter
-// c = w % kClaimers.
+// Per-slot words of the barrier-based iteration (unsigned long long, one
+// 128-byte line per slot).  Wavefront w uses slot c = w % kClaimers: it
+// claims the items c + kClaimers * k from the slot's counter and adds its
+// statistics there, so no word is updated by every wavefront.
 constexpr int kClaimers = 16;
 constexpr int kClaimStride = 16;
+enum SlotWord {
+  kSlotClaim = 0,     // claim counter (reset after each iteration)
+  kSlotVertices = 1,  // rank recomputations of the call
+  kSlotEdges = 2,     // in-edges gathered (self-loops included)
+  kSlotOut = 3,       // out-edges scanned by frontier expansion
+  kSlotNewly = 4,     // vertices newly affected in this iteration
+  kSlotMaxDr = 5      // largest rank change of this iteration (fp64 bits)
+};
 
 // Device control block of one graph.  The words every wavefront of the
 // persistent kernel touches sit on cache lines of their own.

@@ -109,6 +109,19 @@ struct WaveLds {
   float accf[sizeof(T) == 4 ? kRows : 1];  // fp32 sums (fp32 rows below it)
 };
 
+// The calling wavefront's WaveLds, from the launch's dynamic LDS (one per
+// wavefront of the workgroup: launch with lds_bytes<T>(block_size)).
+template <typename T>
+__device__ __forceinline__ WaveLds<T> &wave_lds() {
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
+  return reinterpret_cast<WaveLds<T> *>(dyn_lds)[threadIdx.x / kWave];
+}
+
+template <typename T>
+constexpr size_t lds_bytes(int block_size) {
+  return sizeof(WaveLds<T>) * (size_t)(block_size / kWave);
+}
+
 // Orders LDS traffic of the lanes of one wavefront (no cross-wave sync).
 __device__ __forceinline__ void wave_lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -574,8 +587,7 @@ __device__ __forceinline__ unsigned long long groups_per_claim(int chunk) {
 // The lock-free persistent kernel for one graph.
 template <typename T>
 __global__ void __launch_bounds__(256) k_df_async(RankArgs<T> A) {
-  __shared__ WaveLds<T> lds[256 / kWave];
-  WaveLds<T> &L = lds[threadIdx.x / kWave];
+  WaveLds<T> &L = wave_lds<T>();
   const int lane = lane_id();
   Counters cnt;
   long long newly = 0;
@@ -608,8 +620,7 @@ __global__ void __launch_bounds__(256) k_df_async_many(const RankArgs<T> *descs,
                                                        int count, int *done_count,
                                                        int *abort_flag,
                                                        unsigned long long timeout_ticks) {
-  __shared__ WaveLds<T> lds[256 / kWave];
-  WaveLds<T> &L = lds[threadIdx.x / kWave];
+  WaveLds<T> &L = wave_lds<T>();
   const int lane = lane_id();
   const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   int gi = (int)(wave % count);
@@ -658,8 +669,7 @@ template <typename T, int MODE>
 __global__ void __launch_bounds__(256) k_sync_iter(RankArgs<T> A, int iter,
                                                    const int32_t *steps) {
   if (A.ctl->sync_done) return;
-  __shared__ WaveLds<T> lds[256 / kWave];
-  WaveLds<T> &L = lds[threadIdx.x / kWave];
+  WaveLds<T> &L = wave_lds<T>();
   const int lane = lane_id();
   Counters cnt;
   double maxdr = 0.0;
@@ -696,12 +706,41 @@ __global__ void __launch_bounds__(256) k_sync_iter(RankArgs<T> A, int iter,
     process_step<T, MODE>(A, L, vv, cnt, maxdr, newly, unused_moved);
   }
   maxdr = wave_max(maxdr);
-  if (lane == 0 && maxdr > 0.0)
-    atomicMax(&A.sync_max[iter], (unsigned long long)__double_as_longlong(maxdr));
-  flush_counters<T>(A.ctl, cnt);
+  const unsigned long long v = wave_sum(cnt.vertices);
+  const unsigned long long e = wave_sum(cnt.edges);
+  const unsigned long long o = wave_sum(cnt.out_scanned);
   newly = wave_sum(newly);
-  if (lane == 0 && newly)
-    atomicAdd((unsigned long long *)&A.ctl->newly, (unsigned long long)newly);
+  if (lane == 0) {
+    unsigned long long *slot = A.sync_grab + c * kClaimStride;
+    if (maxdr > 0.0)
+      atomicMax(slot + kSlotMaxDr, (unsigned long long)__double_as_longlong(maxdr));
+    if (v) atomicAdd(slot + kSlotVertices, v);
+    if (e) atomicAdd(slot + kSlotEdges, e);
+    if (o) atomicAdd(slot + kSlotOut, o);
+    if (newly) atomicAdd(slot + kSlotNewly, (unsigned long long)newly);
+  }
+}
+
+// Sum of the slots' newly-affected counts.
+__device__ __forceinline__ unsigned long long slots_newly(const unsigned long long *slots) {
+  unsigned long long t = 0;
+#pragma unroll
+  for (int c = 0; c < kClaimers; ++c) t += slots[c * kClaimStride + kSlotNewly];
+  return t;
+}
+
+// Call totals of the slots into the control block (after the loop).
+__global__ void k_slot_totals(const unsigned long long *slots, Ctl *ctl) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  unsigned long long v = 0, e = 0, o = 0;
+  for (int c = 0; c < kClaimers; ++c) {
+    v += slots[c * kClaimStride + kSlotVertices];
+    e += slots[c * kClaimStride + kSlotEdges];
+    o += slots[c * kClaimStride + kSlotOut];
+  }
+  ctl->vertices = v;
+  ctl->edges = e;
+  ctl->out_scanned = o;
 }
 
 // Marks the out-neighbours of the long out-rows deferred by the iteration
@@ -711,7 +750,8 @@ __global__ void __launch_bounds__(256) k_expand_long(const int32_t *xrow,
                                                      const int64_t *out_off,
                                                      const int32_t *out_deg,
                                                      const int32_t *out_adj,
-                                                     uint32_t *flags, Ctl *ctl) {
+                                                     uint32_t *flags, Ctl *ctl,
+                                                     unsigned long long *slots) {
   const unsigned long long nx = ctl->nexp;
   long long newly = 0;
   for (unsigned long long j = blockIdx.x; j < nx; j += gridDim.x) {
@@ -723,20 +763,32 @@ __global__ void __launch_bounds__(256) k_expand_long(const int32_t *xrow,
   }
   newly = wave_sum(newly);
   if (lane_id() == 0 && newly)
-    atomicAdd((unsigned long long *)&ctl->newly, (unsigned long long)newly);
+    atomicAdd(slots + (blockIdx.x % kClaimers) * kClaimStride + kSlotNewly,
+              (unsigned long long)newly);
 }
 
-__global__ void k_sync_finish(Ctl *ctl, const unsigned long long *sync_max,
+// One wavefront: the iteration's largest change from the slots, the
+// convergence decision, and the slot words reset for the next iteration.
+__global__ void k_sync_finish(Ctl *ctl, unsigned long long *sync_max,
                               unsigned long long *sync_len,
-                              unsigned long long *claims, int iter,
+                              unsigned long long *slots, int iter,
                               double tol, int max_iters, int df) {
-  if (threadIdx.x < kClaimers) claims[threadIdx.x * kClaimStride] = 0;
-  if (threadIdx.x == 0) {
-    ctl->newly = 0;
-    ctl->nexp = 0;
+  const int t = threadIdx.x;
+  unsigned long long bits = 0;
+  if (t < kClaimers) {
+    unsigned long long *slot = slots + t * kClaimStride;
+    bits = slot[kSlotMaxDr];
+    slot[kSlotClaim] = 0;
+    slot[kSlotNewly] = 0;
+    slot[kSlotMaxDr] = 0;
   }
-  if (threadIdx.x != 0 || ctl->sync_done) return;
-  const double md = __longlong_as_double((long long)sync_max[iter]);
+  // non-negative doubles order like their bit patterns
+  bits = wave_max(bits);
+  if (t != 0) return;
+  ctl->nexp = 0;
+  if (ctl->sync_done) return;
+  sync_max[iter] = bits;
+  const double md = __longlong_as_double((long long)bits);
   if (md <= tol || iter + 1 >= max_iters) {
     ctl->sync_done = 1;
     ctl->sync_final = iter + 1;
@@ -754,7 +806,7 @@ __global__ void k_sync_begin(Ctl *ctl, unsigned long long *sync_max,
     sync_max[i] = 0;
     sync_len[i] = 0;
   }
-  if (blockIdx.x == 0 && threadIdx.x < kClaimers) sync_grab[threadIdx.x * kClaimStride] = 0;
+  if (blockIdx.x == 0 && threadIdx.x < kClaimers * kClaimStride) sync_grab[threadIdx.x] = 0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     sync_len[0] = ctl->nsteps | (ctl->npieces << 32);
     ctl->sync_done = 0;
@@ -1025,12 +1077,12 @@ RankArgs<T> make_args(dfpr_graph *g, int rd, int wr) {
 // field of the scheduling word holds 16 bits, so the grid stays below 32768
 // wavefronts; chunk <= 4096 keeps cursor overshoot far below 2^32.
 template <typename K>
-int persistent_blocks(dfpr_graph *g, K kernel) {
+int persistent_blocks(dfpr_graph *g, K kernel, size_t lds) {
   int blocks = g->p.grid_blocks;
   if (blocks <= 0) {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel,
-                                                     g->p.block_size, 0) != hipSuccess ||
+                                                     g->p.block_size, lds) != hipSuccess ||
         per_cu < 1)
       per_cu = 1;
     blocks = per_cu * g->cu_count;
@@ -1063,6 +1115,7 @@ double algorithmic_bytes(const dfpr_graph *g, const Ctl &h) {
 // Totals land in ctl->tail / nsteps / nlong / npieces.  Rows of fewer
 // in-edges are never split, so a step can exceed kStepEdges by one row.
 constexpr int32_t kStepEdges = 16384;
+constexpr int kSyncWavesPerCU = 14;
 
 struct TileSum {
   int32_t sel, steps, nlong, pieces;
@@ -1135,8 +1188,9 @@ template <bool ALL>
 __global__ void __launch_bounds__(256) k_tile_count(const uint8_t *flags,
                                                     const int32_t *deg, int32_t n,
                                                     int32_t split, TileSum *sums,
-                                                    const Ctl *ctl, int reuse) {
-  if (reuse && ctl->newly == 0) return;  // nothing newly affected: keep
+                                                    const unsigned long long *slots,
+                                                    int reuse) {
+  if (reuse && slots_newly(slots) == 0) return;  // nothing newly affected: keep
   const TileScan r = tile_scan<ALL>(flags, deg, n, split);
   if (threadIdx.x == 0) {
     sums[blockIdx.x] = r.tot;
@@ -1149,8 +1203,10 @@ __global__ void __launch_bounds__(256) k_tile_emit(const uint8_t *flags,
                                                    const int32_t *deg, int32_t n,
                                                    int32_t split, const TileSum *pre,
                                                    int32_t *wl, int32_t *steps,
-                                                   Split S, Ctl *ctl, int reuse) {
-  if (reuse && ctl->newly == 0) return;
+                                                   Split S, Ctl *ctl,
+                                                   const unsigned long long *slots,
+                                                   int reuse) {
+  if (reuse && slots_newly(slots) == 0) return;
   const TileScan r = tile_scan<ALL>(flags, deg, n, split);
   const TileSum b = pre[blockIdx.x];
   if (r.sel) {
@@ -1226,10 +1282,10 @@ int build_items(dfpr_graph *g, bool all, bool reuse) {
   const uint8_t *fl = reinterpret_cast<const uint8_t *>(g->flags);
   const int32_t split = g->p.split_min_degree;
   if (all)
-    k_tile_count<true><<<nt, 256, 0, s>>>(fl, g->in.deg, g->n, split, sums, g->ctl, 0);
+    k_tile_count<true><<<nt, 256, 0, s>>>(fl, g->in.deg, g->n, split, sums, g->sync_grab, 0);
   else
-    k_tile_count<false><<<nt, 256, 0, s>>>(fl, g->in.deg, g->n, split, sums, g->ctl,
-                                           reuse);
+    k_tile_count<false><<<nt, 256, 0, s>>>(fl, g->in.deg, g->n, split, sums,
+                                           g->sync_grab, reuse);
   DFPR_HIP(hipGetLastError());
   size_t tb = 0;
   const TileSum zero{0, 0, 0, 0};
@@ -1241,10 +1297,10 @@ int build_items(dfpr_graph *g, bool all, bool reuse) {
                                    TileSumPlus(), s));
   if (all)
     k_tile_emit<true><<<nt, 256, 0, s>>>(fl, g->in.deg, g->n, split, pre, g->wl, g->steps,
-                                         g->split, g->ctl, 0);
+                                         g->split, g->ctl, g->sync_grab, 0);
   else
     k_tile_emit<false><<<nt, 256, 0, s>>>(fl, g->in.deg, g->n, split, pre, g->wl, g->steps,
-                                          g->split, g->ctl, reuse);
+                                          g->split, g->ctl, g->sync_grab, reuse);
   DFPR_HIP(hipGetLastError());
   return DFPR_OK;
 }
@@ -1268,7 +1324,21 @@ int run_sync(dfpr_graph *g, int mode, dfpr_stats *st) {
   k_sync_begin<<<4, 256, 0, s>>>(g->ctl, g->sync_max, g->sync_grab, g->sync_len, iters);
   DFPR_HIP(hipGetLastError());
   auto kern = mode == kAll ? k_sync_iter<T, kAll> : k_sync_iter<T, kSyncDF>;
-  const int blocks = persistent_blocks(g, kern);
+  const size_t lds = lds_bytes<T>(g->p.block_size);
+  int blocks = persistent_blocks(g, kern, lds);
+  if (g->p.grid_blocks <= 0) {
+    // no more wavefronts than an iteration can have items (tiles, edge
+    // steps, pieces), and at most kSyncWavesPerCU per CU: measured on the
+    // 2^22 R-MAT, 14 per CU beat both 8 and the 20 that fit
+    const int wpb = g->p.block_size / kWave;
+    const int64_t nt = ((int64_t)g->n + kRows - 1) / kRows;
+    const int64_t items = nt + g->in.adj_cap / kStepEdges + 1 + g->split.pcap;
+    int64_t want = (items + wpb - 1) / wpb;
+    const int64_t cap = (int64_t)kSyncWavesPerCU * (g->cu_count > 0 ? g->cu_count : 1) / wpb;
+    if (want > cap) want = cap;
+    if (want < 1) want = 1;
+    if (want < blocks) blocks = (int)want;
+  }
   const int xgrid = g->cu_count > 0 ? g->cu_count : 1;
   while ((int)g->iter_ev.size() < 2 * iters) {
     hipEvent_t e = nullptr;
@@ -1281,11 +1351,11 @@ int run_sync(dfpr_graph *g, int mode, dfpr_stats *st) {
   for (; it < iters; ++it) {
     RankArgs<T> A = make_args<T>(g, (g->cur + it) & 1, (g->cur + it + 1) & 1);
     DFPR_HIP(hipEventRecord(g->iter_ev[2 * it], s));
-    kern<<<blocks, g->p.block_size, 0, s>>>(A, it, g->steps);
+    kern<<<blocks, g->p.block_size, lds, s>>>(A, it, g->steps);
     DFPR_HIP(hipEventRecord(g->iter_ev[2 * it + 1], s));
     if (mode != kAll) {
       k_expand_long<<<xgrid, 256, 0, s>>>(g->split.xrow, g->out.off, g->out.deg,
-                                          g->out.adj, g->flags, g->ctl);
+                                          g->out.adj, g->flags, g->ctl, g->sync_grab);
       int rc = build_items(g, false, true);
       if (rc) return rc;
     }
@@ -1299,6 +1369,8 @@ int run_sync(dfpr_graph *g, int mode, dfpr_stats *st) {
     }
   }
   DFPR_HIP(hipEventRecord(g->ev[2], s));
+  k_slot_totals<<<1, 64, 0, s>>>(g->sync_grab, g->ctl);
+  DFPR_HIP(hipGetLastError());
   DFPR_HIP(hipMemcpyAsync(g->h_ctl, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
   DFPR_HIP(hipStreamSynchronize(s));
   const Ctl h = *g->h_ctl;
@@ -1344,12 +1416,13 @@ int run_async(dfpr_graph *g, dfpr_stats *st) {
   DFPR_HIP(hipMemcpyAsync(g->h_ctl, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
   DFPR_HIP(hipStreamSynchronize(s));
   const int waves_per_block = g->p.block_size / kWave;
-  int blocks = persistent_blocks(g, k_df_async<T>);
+  const size_t lds = lds_bytes<T>(g->p.block_size);
+  int blocks = persistent_blocks(g, k_df_async<T>, lds);
   const long long groups = (long long)g->h_ctl->gtail;
   const long long want = (groups + waves_per_block - 1) / waves_per_block;
   if (want < blocks) blocks = (int)(want > 0 ? want : 1);
   DFPR_HIP(hipEventRecord(g->ev[1], s));
-  k_df_async<T><<<blocks, g->p.block_size, 0, s>>>(A);
+  k_df_async<T><<<blocks, g->p.block_size, lds, s>>>(A);
   DFPR_HIP(hipGetLastError());
   DFPR_HIP(hipEventRecord(g->ev[2], s));
   DFPR_HIP(hipMemcpyAsync(g->h_ctl, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
@@ -1546,14 +1619,15 @@ int update_many_t(dfpr_graph *const *gs, int32_t count, dfpr_stats *stats) {
   long long groups = 0;
   for (const Summary &x : hs) groups += (long long)x.gtail;
   const int wpb = g0->p.block_size / kWave;
-  int blocks = persistent_blocks(g0, k_df_async_many<T>);
+  const size_t lds = lds_bytes<T>(g0->p.block_size);
+  int blocks = persistent_blocks(g0, k_df_async_many<T>, lds);
   const long long want = (groups + wpb - 1) / wpb;
   if (want < blocks) blocks = (int)(want > 0 ? want : 1);
   const unsigned long long ticks =
       g0->p.timeout_ms > 0 ? (unsigned long long)g0->p.timeout_ms * (unsigned long long)g0->wallclock_khz
                            : 0ull;
   DFPR_HIP(hipEventRecord(g0->ev[0], s));
-  k_df_async_many<T><<<blocks, g0->p.block_size, 0, s>>>(d_desc, na, d_done, &g0->ctl->abort,
+  k_df_async_many<T><<<blocks, g0->p.block_size, lds, s>>>(d_desc, na, d_done, &g0->ctl->abort,
                                                          ticks);
   DFPR_HIP(hipGetLastError());
   DFPR_HIP(hipEventRecord(g0->ev[1], s));
