@@ -89,9 +89,10 @@ typedef struct {
                                wavefronts (partial sums added in piece
                                order), the rest in edge-balanced steps of
                                up to 256 rows                              */
-  int32_t chunk;         /* lock-free scheme: worklist groups per dynamic
-                            grab are chunk / 256 (at least one); a multiple
-                            of 64 in [64, 4096]                             */
+  int32_t chunk;         /* lock-free scheme: vertices per claim, whole
+                            256-vertex groups (chunk / 256, at least one); a
+                            multiple of 64 in [64, 4096], or 0 (default):
+                            one group per 4096 groups of the graph, 1..16  */
   int32_t block_size;    /* threads per workgroup: 64, 128 (default), 192 or
                             256                                             */
   int32_t reorder;       /* internal vertex order, fixed at creation:

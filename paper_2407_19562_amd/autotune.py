@@ -13,7 +13,8 @@ Spaces:
   sync    one graph, barrier-based scheme: the in-degree at which rows are
           summed in pieces (split_min_degree) and the workgroup size.
   async   one graph or many in one persistent launch (lock-free scheme):
-          groups per claim (chunk / 256) and the workgroup size.
+          groups per claim (chunk / 256; 0 = the library's choice) and the
+          workgroup size.
 
 Call it between updates (no applied batch may be pending).  The winner is
 set on every graph and returned with the table of timings.  If a trial
@@ -28,9 +29,9 @@ from . import dfpr, inputs
 
 SPACES = {
     "sync": [{"split_min_degree": s, "block_size": b}
-             for s in (512, 1024, 2048, 4096) for b in (128, 256)],
+             for s in (1024, 2048, 4096) for b in (128, 256)],
     "async": [{"chunk": c, "block_size": b}
-              for c in (256, 512, 1024) for b in (64, 128, 256)],
+              for c in (0, 256, 1024, 4096) for b in (64, 128, 256)],
 }
 
 

@@ -59,8 +59,8 @@ int check_params(const dfpr_params *p) {
   if (p->mode != DFPR_ASYNC && p->mode != DFPR_SYNC) return fail(DFPR_EINVAL, "bad mode");
   if (p->split_min_degree < 1) return fail(DFPR_EINVAL, "split_min_degree must be >= 1");
   if (p->kahan_min_degree < 0) return fail(DFPR_EINVAL, "kahan_min_degree must be >= 0");
-  if (p->chunk < 64 || p->chunk % 64 || p->chunk > 4096)
-    return fail(DFPR_EINVAL, "chunk must be a multiple of 64 in [64, 4096]");
+  if (p->chunk != 0 && (p->chunk < 64 || p->chunk % 64 || p->chunk > 4096))
+    return fail(DFPR_EINVAL, "chunk must be 0 or a multiple of 64 in [64, 4096]");
   if (p->block_size < 64 || p->block_size > 256 || p->block_size % 64)
     return fail(DFPR_EINVAL, "block_size must be 64, 128, 192 or 256");
   if (p->timeout_ms < 0) return fail(DFPR_EINVAL, "timeout_ms must be >= 0");
@@ -166,7 +166,7 @@ int dfpr_params_default(dfpr_params *p) {
   p->mode = DFPR_ASYNC;
   p->kahan_min_degree = 64;
   p->split_min_degree = 2048;
-  p->chunk = 256;
+  p->chunk = 0;
   p->block_size = 128;
   p->reorder = 2;
   p->renormalize = 0;

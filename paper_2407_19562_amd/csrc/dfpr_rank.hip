@@ -1031,6 +1031,39 @@ inline int grid_for(int64_t work, int cu) {
   return (int)(b < 1 ? 1 : b);
 }
 
+// Lock-free scheme: vertices per claim (whole 256-vertex groups).  chunk 0
+// picks one group per 4096 groups of the graph, between 1 and 16: on the
+// 2^22 R-MAT (16384 groups) four groups per claim ran 2.5x faster than one.
+inline int effective_chunk(const dfpr_graph *g) {
+  if (g->p.chunk > 0) return g->p.chunk;
+  int per = g->ngroups / 4096;
+  per = per < 1 ? 1 : (per > 16 ? 16 : per);
+  return per * kGroup;
+}
+
+// Lock-free grid: enough wavefronts that each takes about kChunksPerWave
+// claims per sweep.  With more claim holders than a sweep has chunks, new
+// sweeps start over groups still being processed and every wavefront
+// contends for the one scheduling word (the 2^22 R-MAT ran 8x slower with
+// every co-resident wavefront than with a quarter of them).
+constexpr int kChunksPerWave = 4;
+
+inline long long claim_chunks(const dfpr_graph *g, unsigned long long gtail) {
+  const long long per = effective_chunk(g) / kGroup;
+  return ((long long)gtail + per - 1) / per;
+}
+
+// Wavefronts for `chunks` claimable chunks per sweep: one per chunk up to
+// four per CU (small graphs: C1's 64 groups ran 3.7x faster with 64
+// wavefronts than with 16), beyond that one per kChunksPerWave chunks.
+inline long long async_waves(long long chunks, int cu_count) {
+  const long long floor_w = 4ll * (cu_count > 0 ? cu_count : 1);
+  long long w = (chunks + kChunksPerWave - 1) / kChunksPerWave;
+  if (w < floor_w) w = floor_w;
+  if (w > chunks) w = chunks;
+  return w > 0 ? w : 1;
+}
+
 template <typename T>
 RankArgs<T> make_args(dfpr_graph *g, int rd, int wr) {
   RankArgs<T> A;
@@ -1056,7 +1089,7 @@ RankArgs<T> make_args(dfpr_graph *g, int rd, int wr) {
   A.ftol = g->p.frontier_tol;
   A.split_min = g->p.split_min_degree;
   A.kahan_min = g->p.kahan_min_degree;
-  A.chunk = g->p.chunk;
+  A.chunk = effective_chunk(g);
   A.max_iters = g->p.max_iters;
   A.timeout_ticks = g->p.timeout_ms > 0
                         ? (unsigned long long)g->p.timeout_ms * (unsigned long long)g->wallclock_khz
@@ -1410,17 +1443,17 @@ int run_async(dfpr_graph *g, dfpr_stats *st) {
   k_async_begin<<<1, 64, 0, s>>>(g->ctl);
   DFPR_HIP(hipGetLastError());
   RankArgs<T> A = make_args<T>(g, g->cur, g->cur);
-  // At most one wavefront per listed group: with more, idle wavefronts
-  // would start new sweeps over groups still being processed and a sweep
-  // would stop meaning one pass over the affected groups.
+  // grid from the groups listed by the marking (kChunksPerWave)
   DFPR_HIP(hipMemcpyAsync(g->h_ctl, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
   DFPR_HIP(hipStreamSynchronize(s));
   const int waves_per_block = g->p.block_size / kWave;
   const size_t lds = lds_bytes<T>(g->p.block_size);
   int blocks = persistent_blocks(g, k_df_async<T>, lds);
-  const long long groups = (long long)g->h_ctl->gtail;
-  const long long want = (groups + waves_per_block - 1) / waves_per_block;
-  if (want < blocks) blocks = (int)(want > 0 ? want : 1);
+  if (g->p.grid_blocks <= 0) {
+    const long long waves = async_waves(claim_chunks(g, g->h_ctl->gtail), g->cu_count);
+    const long long want = (waves + waves_per_block - 1) / waves_per_block;
+    if (want < blocks) blocks = (int)(want > 0 ? want : 1);
+  }
   DFPR_HIP(hipEventRecord(g->ev[1], s));
   k_df_async<T><<<blocks, g->p.block_size, lds, s>>>(A);
   DFPR_HIP(hipGetLastError());
@@ -1616,13 +1649,16 @@ int update_many_t(dfpr_graph *const *gs, int32_t count, dfpr_stats *stats) {
   std::vector<Summary> hs(na);
   DFPR_HIP(hipMemcpyAsync(hs.data(), d_sum, sbytes, hipMemcpyDeviceToHost, s));
   DFPR_HIP(hipStreamSynchronize(s));
-  long long groups = 0;
-  for (const Summary &x : hs) groups += (long long)x.gtail;
+  long long chunks = 0;
+  for (int i = 0; i < na; ++i) chunks += claim_chunks(act[i], hs[i].gtail);
   const int wpb = g0->p.block_size / kWave;
   const size_t lds = lds_bytes<T>(g0->p.block_size);
   int blocks = persistent_blocks(g0, k_df_async_many<T>, lds);
-  const long long want = (groups + wpb - 1) / wpb;
-  if (want < blocks) blocks = (int)(want > 0 ? want : 1);
+  if (g0->p.grid_blocks <= 0) {
+    const long long waves = async_waves(chunks, g0->cu_count);
+    const long long want = (waves + wpb - 1) / wpb;
+    if (want < blocks) blocks = (int)(want > 0 ? want : 1);
+  }
   const unsigned long long ticks =
       g0->p.timeout_ms > 0 ? (unsigned long long)g0->p.timeout_ms * (unsigned long long)g0->wallclock_khz
                            : 0ull;
