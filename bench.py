@@ -60,6 +60,11 @@ def parse():
                     help="graph count for batched1024 / serving")
     ap.add_argument("--requests", type=int, default=None,
                     help="update batches in the serving stream")
+    ap.add_argument("--scheme", default="each", choices=["batched", "each"],
+                    help="serving: one batched lock-free launch per round, or "
+                         "barrier-based updates graph by graph")
+    ap.add_argument("--max-graphs", type=int, default=8,
+                    help="serving: graphs per round (0: all with queued requests)")
     ap.add_argument("--param", action="append", default=[],
                     help="library parameter override name=value")
     return ap.parse_args()

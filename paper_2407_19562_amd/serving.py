@@ -4,11 +4,12 @@ applied with continuous batching.
 Every graph keeps its slack CSR and ranks resident on the device.  Requests
 (one update batch for one graph) queue per graph in arrival order.  The
 loop runs in rounds: each round admits the requests that have arrived (as
-long as free device memory covers their staging), applies every admitted
-graph's queued batches in FIFO order (at most `coalesce` per graph; batches
+long as free device memory covers their staging), picks the graphs with
+queued requests (at most `max_graphs`, longest-waiting first), applies
+their queued batches in FIFO order (at most `coalesce` per graph; batches
 applied before one update accumulate their marks, which is the same as
-applying their union), and then updates all those graphs together in one
-persistent launch (dfpr_update_many).  A request completes when the round
+applying their union), and then updates those graphs, together in one
+persistent launch (dfpr_update_many) or one by one.  A request completes when the round
 that applied it finishes; its latency runs from arrival to that moment.
 Requests arriving during a round join the next one.
 """
@@ -42,6 +43,9 @@ class Report:
     edges_gathered: int = 0
     batch_edges: int = 0
     admission_waits: int = 0
+    apply_s: float = 0.0      # time spent applying batches (batched scheme)
+    update_s: float = 0.0     # time spent in rank updates (each scheme:
+                              # applies and updates, overlapped)
 
     def summary(self):
         lat = np.array(self.latencies_ms) if self.latencies_ms else np.zeros(1)
@@ -54,24 +58,55 @@ class Report:
                 "edges_gathered_per_s": self.edges_gathered / max(self.wall_s, 1e-9),
                 "rounds": self.rounds, "updates": self.updates,
                 "admission_waits": self.admission_waits,
+                "apply_s": self.apply_s, "update_s": self.update_s,
                 "wall_s": self.wall_s}
 
 
 class Server:
-    """Resident graphs plus the continuous-batching loop."""
+    """Resident graphs plus the continuous-batching loop.
+
+    scheme "batched": each round updates its graphs together in one
+    persistent lock-free launch (dfpr_update_many).  scheme "each"
+    (default): each graph has its own stream, and a round applies and
+    updates each of its graphs (barrier-based scheme) from a worker thread,
+    so the graphs' work overlaps on the device.  A round takes at most `max_graphs`
+    graphs (0: all with queued requests), those whose oldest request has
+    waited longest, so a round stays short under load."""
 
     def __init__(self, graphs, precision: int = 32, coalesce: int = 16,
-                 reserve_bytes: int = 1 << 30, **params):
+                 reserve_bytes: int = 1 << 30, scheme: str = "each",
+                 max_graphs: int = 8, **params):
+        if scheme not in ("batched", "each"):
+            raise ValueError("scheme must be 'batched' or 'each'")
+        self.scheme = scheme
+        mode = dfpr.DFPR_ASYNC if scheme == "batched" else dfpr.DFPR_SYNC
         self.graphs = []
+        self.streams = []
+        self.pool = None
+        if scheme == "each":
+            # every graph on its own stream, and a round's graphs applied and
+            # updated from worker threads, so their work overlaps on the
+            # device (the library's calls release the interpreter lock)
+            import concurrent.futures
+            import torch
+            self.pool = concurrent.futures.ThreadPoolExecutor(max(1, max_graphs or 8))
         for n, s, d in graphs:
-            g = dfpr.Graph(n, s, d, precision=precision, mode=dfpr.DFPR_ASYNC,
-                           renormalize=int(precision == 32), **params)
+            stream = None
+            if scheme == "each":
+                st = torch.cuda.Stream()
+                self.streams.append(st)
+                stream = dfpr.ctypes.c_void_p(st.cuda_stream)
+            g = dfpr.Graph(n, s, d, precision=precision, mode=mode,
+                           renormalize=int(precision == 32), stream=stream, **params)
             g.static()
             self.graphs.append(g)
         self.coalesce = coalesce
+        self.max_graphs = max_graphs
         self.reserve = reserve_bytes
 
     def close(self):
+        if self.pool is not None:
+            self.pool.shutdown()
         for g in self.graphs:
             g.close()
 
@@ -105,6 +140,10 @@ class Server:
                 free -= 48 * r.batch.size
                 queues[r.graph].append(pending.popleft())
             active = [i for i, q in enumerate(queues) if q]
+            if self.max_graphs and len(active) > self.max_graphs:
+                # the graphs whose oldest request waits longest go first
+                active.sort(key=lambda i: queues[i][0].arrival)
+                active = sorted(active[:self.max_graphs])
             if not active:
                 if pending:
                     wait = pending[0].arrival - (time.perf_counter() - t0)
@@ -112,15 +151,29 @@ class Server:
                         time.sleep(min(wait, 0.05))
                 continue
             served = []
+            take = {}
             for i in active:
-                for _ in range(min(self.coalesce, len(queues[i]))):
-                    r = queues[i].popleft()
-                    self.graphs[i].apply(r.batch)
-                    rep.batch_edges += r.batch.size
-                    served.append(r)
-            rc, stats = dfpr.dfpr_update_many([self.graphs[i].h for i in active])
-            if rc < 0:
-                raise dfpr.DfprError(rc, "dfpr_update_many")
+                take[i] = [queues[i].popleft()
+                           for _ in range(min(self.coalesce, len(queues[i])))]
+                served.extend(take[i])
+                rep.batch_edges += sum(r.batch.size for r in take[i])
+            ta = time.perf_counter()
+            if self.scheme == "batched":
+                for i in active:
+                    for r in take[i]:
+                        self.graphs[i].apply(r.batch)
+                tu = time.perf_counter()
+                rc, stats = dfpr.dfpr_update_many([self.graphs[i].h for i in active])
+                rep.apply_s += tu - ta
+                rep.update_s += time.perf_counter() - tu
+            else:
+                def work(i):
+                    g = self.graphs[i]
+                    for r in take[i]:
+                        g.apply(r.batch)
+                    return g.update()[1]
+                stats = list(self.pool.map(work, active))
+                rep.update_s += time.perf_counter() - ta
             end = time.perf_counter() - t0
             rep.rounds += 1
             rep.updates += len(active)
@@ -174,13 +227,13 @@ def bench(args, torch, dfpr_mod, inputs_mod, log):
     """Serving benchmark: resident R-MAT graphs, closed-loop saturated
     throughput X, then open-loop Poisson streams at 0.5 X and 0.8 X."""
     count = args.graphs or 64
-    nreq = args.requests or 5000
+    nreq = args.requests or 20000
     t0 = time.time()
     graphs = list(inputs.resident_mix(count, 4000))
     log(f"{count} resident graphs generated in {time.time() - t0:.1f}s, "
         f"{sum(s.size for _, s, _ in graphs)} edges")
     sizes = [s.size for _, s, _ in graphs]
-    srv = Server(graphs, precision=32)
+    srv = Server(graphs, precision=32, scheme=args.scheme, max_graphs=args.max_graphs)
     try:
         res = {}
         closed = make_stream(sizes, nreq, 4, None, edges_of=lambda g: graphs[g])
@@ -206,5 +259,6 @@ def bench(args, torch, dfpr_mod, inputs_mod, log):
                        "stream": f"{nreq} batches, sizes log-uniform 1..1e5 edges "
                        "(at most 1% of the graph), 80/20, target uniform",
                        "ranks": "fp32 storage and sums, fp64 change tests and "
-                       "renormalisation", "coalesce": srv.coalesce},
+                       "renormalisation", "coalesce": srv.coalesce,
+                       "scheme": srv.scheme, "max_graphs": srv.max_graphs},
             "results": res}

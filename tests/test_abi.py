@@ -85,3 +85,30 @@ def test_strerror_and_bad_params(lib):
     p = lib.dfpr_params_default(alpha=1.5)
     assert h.dfpr_graph_create(4, 0, None, None, 0, ctypes.byref(p), None,
                                ctypes.byref(out)) == lib.DFPR_EINVAL
+
+
+@pytest.mark.parametrize("field,value", [
+    ("chunk", 32), ("chunk", 100), ("chunk", 8192), ("block_size", 96),
+    ("block_size", 512), ("reorder", 3), ("split_min_degree", 0),
+    ("kahan_min_degree", -1), ("max_iters", 0), ("max_iters", 9000),
+    ("precision", 16), ("grid_blocks", 1 << 20), ("timeout_ms", -5)])
+def test_invalid_parameters_are_rejected_before_any_device_call(lib, field, value):
+    h = lib._lib()
+    out = ctypes.c_void_p()
+    p = lib.dfpr_params_default(**{field: value})
+    assert h.dfpr_graph_create(4, 0, None, None, 0, ctypes.byref(p), None,
+                               ctypes.byref(out)) == lib.DFPR_EINVAL
+    assert field.split("_")[0] in lib.dfpr_last_error()
+
+
+def test_automatic_chunk_and_grid_are_valid(lib):
+    # chunk 0 and grid_blocks 0 (the defaults) pass validation: on a host
+    # without a device the call fails later, with a device error
+    h = lib._lib()
+    out = ctypes.c_void_p()
+    p = lib.dfpr_params_default()
+    assert p.chunk == 0 and p.grid_blocks == 0 and p.block_size == 128
+    rc = h.dfpr_graph_create(4, 0, None, None, 0, ctypes.byref(p), None, ctypes.byref(out))
+    assert rc != lib.DFPR_EINVAL
+    if rc == lib.DFPR_OK:
+        h.dfpr_graph_destroy(out)

@@ -19,16 +19,17 @@ def D():
     return dfpr
 
 
-def test_served_equals_alone_and_oracle(D):
+@pytest.mark.parametrize("scheme", ["batched", "each"])
+def test_served_equals_alone_and_oracle(D, scheme):
     import oracle
     from paper_2407_19562_amd import serving
-    print("serving mix", flush=True)
+    print("serving mix", scheme, flush=True)
     graphs = [inputs.rmat(11 + (i % 3), (8 + 4 * (i % 2)) << (11 + (i % 3)), seed=70 + i)
               for i in range(6)]
     sizes = [s.size for _, s, _ in graphs]
     reqs = serving.make_stream(sizes, 48, seed=11, rate=None, lo=1, hi=400,
                                edges_of=lambda g: graphs[g])
-    srv = serving.Server(graphs, precision=32, coalesce=3)
+    srv = serving.Server(graphs, precision=32, coalesce=3, scheme=scheme)
     try:
         rep = srv.run(reqs, open_loop=False)
         s = rep.summary()
