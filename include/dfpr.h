@@ -206,8 +206,9 @@ int dfpr_update_many(dfpr_graph *const *gs, int32_t count, dfpr_stats *stats);
 int dfpr_read_edges(const dfpr_graph *g, int dir, int32_t *src, int32_t *dst,
                     int64_t cap, int64_t *count);
 
-/* Affected flags after the marking / last update (1 byte per vertex) and
- * the number of vertices currently marked; for tests. */
+/* Affected flags after the marking (1 byte per vertex; all zero once an
+ * update has consumed them) and the number of vertices the pending
+ * batches marked; for tests. */
 int dfpr_read_marks(const dfpr_graph *g, uint8_t *affected, int64_t *count);
 
 /* Device bytes held by the graph. */
@@ -219,9 +220,13 @@ int dfpr_graph_bytes(const dfpr_graph *g, int64_t *bytes);
 int dfpr_stream_copy(void *dst, const void *src, int64_t bytes,
                      void *hip_stream, float *ms);
 
-/* Name of the last kernel that dominates dfpr_update / dfpr_static, and
- * its algorithmic byte count for the last call (see the design notes for
- * the per-unit figures): one entry per launch of the rank iteration. */
+/* Algorithmic bytes of the rank kernel launches of the last dfpr_update /
+ * dfpr_static / dfpr_naive_dynamic call and the number of those launches.
+ * Per gathered in-edge 12 bytes (fp64) or 8 (fp32): the 4-byte index and
+ * the contribution; per recomputed vertex 52 or 36: in-row offset 8,
+ * in-degree 4, out-degree 4, worklist entry 4, rank read and write,
+ * contribution write and the vertex's own contribution; per scanned
+ * out-edge 5 (index and flag byte). */
 int dfpr_last_kernel_bytes(const dfpr_graph *g, double *bytes,
                            int32_t *launches);
 

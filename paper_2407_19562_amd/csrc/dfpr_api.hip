@@ -407,7 +407,7 @@ int dfpr_read_marks(const dfpr_graph *g, uint8_t *affected, int64_t *count) {
   }
   if (count) {
     unsigned long long t = 0;
-    DFPR_HIP(hipMemcpyAsync(&t, &g->ctl->tail, 8, hipMemcpyDeviceToHost, g->stream));
+    DFPR_HIP(hipMemcpyAsync(&t, &g->ctl->marked, 8, hipMemcpyDeviceToHost, g->stream));
     DFPR_HIP(hipStreamSynchronize(g->stream));
     *count = (int64_t)t;
   }

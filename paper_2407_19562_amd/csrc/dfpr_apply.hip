@@ -17,8 +17,9 @@
 //     grows the array and re-runs the rows left pending.
 // Marking: for every source u with a real change, u itself (self-loop), its
 // current out-neighbours and the targets of its deleted edges -- together
-// (G^{t-1} union G^t).out(u) -- get the affected and not-converged flags,
-// and newly affected vertices are appended to the worklist.
+// (G^{t-1} union G^t).out(u) -- get the affected flag and their 256-vertex
+// group the listed flag; the vertices marked first are counted.  The
+// update builds its work lists from these flags.
 // Rows of at least kLongApply entries are not left to one wavefront:
 // their deletions run in a second launch with a 1024-thread workgroup per
 // row (segment keys staged in LDS, block-wide compaction), and their
@@ -380,17 +381,13 @@ __global__ void k_mark_sources(int64_t S, const int64_t *segstart,
                                const unsigned long long *uk,
                                const uint8_t *status, AdjView out,
                                const T *R, T *C, uint32_t *flags,
-                               uint32_t *gflags, int32_t *wl, int32_t *gwl,
-                               Ctl *ctl, int32_t *long_list) {
+                               uint32_t *gflags, Ctl *ctl, int32_t *long_list) {
   const int lane = lane_id();
   const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  long long appended = 0;
+  unsigned long long marked = 0;  // vertices this lane marked first
   auto mark = [&](bool act, int32_t v) {
-    MarkOut o{false, false, -1};
-    if (act) o = mark_affected(flags, gflags, v);
-    appended += wave_append(o.vnew, v, wl, &ctl->tail, true);
-    wave_append(o.gnew, o.g, gwl, &ctl->gtail, true);
+    if (act && mark_affected(flags, gflags, v).vnew) ++marked;
   };
   for (int64_t s = wave; s < S; s += nwaves) {
     const int64_t a = segstart[s], b = segstart[s + 1];
@@ -419,35 +416,27 @@ __global__ void k_mark_sources(int64_t S, const int64_t *segstart,
       mark(act, act ? (int32_t)((uk[e] >> 1) & 0x7FFFFFFFull) : -1);
     }
   }
-  if (lane == 0 && appended)
-    atomicAdd((unsigned long long *)&ctl->marked, (unsigned long long)appended);
+  marked = wave_sum(marked);
+  if (lane == 0 && marked) atomicAdd((unsigned long long *)&ctl->marked, marked);
 }
 
 // Out-rows deferred by k_mark_sources: every wavefront of the launch takes
 // its share of 64-entry chunks of every such row.
 __global__ void k_mark_long(const int32_t *long_list, AdjView out, uint32_t *flags,
-                            uint32_t *gflags, int32_t *wl, int32_t *gwl, Ctl *ctl) {
-  const int lane = lane_id();
-  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+                            uint32_t *gflags, Ctl *ctl) {
+  const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t nt = (int64_t)gridDim.x * blockDim.x;
   const unsigned long long cnt = ctl->nlong_mark;
-  long long appended = 0;
+  unsigned long long marked = 0;
   for (unsigned long long j = 0; j < cnt; ++j) {
     const int32_t u = long_list[j];
     const int64_t off = out.off[u];
     const int32_t deg = out.deg[u];
-    for (int64_t base = wave * kWave; base < deg; base += nwaves * kWave) {
-      const int64_t idx = base + lane;
-      const bool act = idx < deg;
-      MarkOut o{false, false, -1};
-      const int32_t v = act ? out.adj[off + idx] : -1;
-      if (act) o = mark_affected(flags, gflags, v);
-      appended += wave_append(o.vnew, v, wl, &ctl->tail, true);
-      wave_append(o.gnew, o.g, gwl, &ctl->gtail, true);
-    }
+    for (int64_t idx = t0; idx < deg; idx += nt)
+      if (mark_affected(flags, gflags, out.adj[off + idx]).vnew) ++marked;
   }
-  if (lane == 0 && appended)
-    atomicAdd((unsigned long long *)&ctl->marked, (unsigned long long)appended);
+  marked = wave_sum(marked);
+  if (lane_id() == 0 && marked) atomicAdd((unsigned long long *)&ctl->marked, marked);
 }
 
 }  // namespace
@@ -614,16 +603,14 @@ int apply_batch(dfpr_graph *g, int64_t nd, const int32_t *ds,
     if (g->elem == 8)
       k_mark_sources<double><<<blocks, 256, 0, s>>>(
           S[0], seg[0], uk[0], st[0], o, (const double *)g->R[g->cur],
-          (double *)g->C[g->cur], g->flags, g->gflags, g->wl, g->gwl, g->ctl,
-          (int32_t *)ml);
+          (double *)g->C[g->cur], g->flags, g->gflags, g->ctl, (int32_t *)ml);
     else
       k_mark_sources<float><<<blocks, 256, 0, s>>>(
           S[0], seg[0], uk[0], st[0], o, (const float *)g->R[g->cur],
-          (float *)g->C[g->cur], g->flags, g->gflags, g->wl, g->gwl, g->ctl,
-          (int32_t *)ml);
+          (float *)g->C[g->cur], g->flags, g->gflags, g->ctl, (int32_t *)ml);
     DFPR_HIP(hipGetLastError());
     k_mark_long<<<cu > 0 ? 4 * cu : 1, 256, 0, s>>>((const int32_t *)ml, o, g->flags,
-                                                   g->gflags, g->wl, g->gwl, g->ctl);
+                                                   g->gflags, g->ctl);
     DFPR_HIP(hipGetLastError());
   }
   DFPR_HIP(hipMemcpyAsync(g->h_ctl, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
@@ -632,7 +619,7 @@ int apply_batch(dfpr_graph *g, int64_t nd, const int32_t *ds,
   if (h.del_applied != h.del_applied_in || h.ins_applied != h.ins_applied_in)
     return fail(DFPR_EHIP, "in/out adjacency disagree after the batch");
   g->m += (int64_t)h.ins_applied - (int64_t)h.del_applied;
-  g->pending_marks = (int64_t)h.tail;
+  g->pending_marks = (int64_t)h.marked;
   if (applied_del) *applied_del = (int64_t)h.del_applied;
   if (applied_ins) *applied_ins = (int64_t)h.ins_applied;
   return DFPR_OK;

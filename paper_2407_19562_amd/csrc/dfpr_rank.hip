@@ -1265,6 +1265,45 @@ __global__ void __launch_bounds__(256) k_tile_emit(const uint8_t *flags,
   }
 }
 
+// Group worklist of the lock-free scheme from the listed flags: one
+// 256-thread workgroup per graph compacts the graph's group flags in id
+// order into gwl and sets gtail.
+__device__ __forceinline__ void list_groups(const uint8_t *gflags, int32_t ngroups,
+                                            int32_t *gwl, unsigned long long *gtail) {
+  __shared__ int32_t lds4[4];
+  int32_t base = 0;
+  for (int32_t g0 = 0; g0 < ngroups; g0 += kRows) {
+    const int32_t gi = g0 + (int32_t)threadIdx.x;
+    const bool sel = gi < ngroups && (gflags[gi] & kGA);
+    int32_t total = 0;
+    const int32_t pos = block_excl_scan(sel ? 1 : 0, lds4, &total);
+    if (sel) gwl[base + pos] = gi;
+    base += total;
+  }
+  if (threadIdx.x == 0) *gtail = (unsigned long long)base;
+}
+
+__global__ void __launch_bounds__(256) k_list_groups(const uint32_t *gflags, int32_t ngroups,
+                                                     int32_t *gwl, Ctl *ctl) {
+  list_groups(reinterpret_cast<const uint8_t *>(gflags), ngroups, gwl, &ctl->gtail);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_list_groups_many(const RankArgs<T> *descs, int count) {
+  for (int i = blockIdx.x; i < count; i += gridDim.x) {
+    const RankArgs<T> &A = descs[i];
+    list_groups(reinterpret_cast<const uint8_t *>(A.gflags), (A.n + kGroup - 1) / kGroup,
+                A.gwl, &A.ctl->gtail);
+    __syncthreads();
+  }
+}
+
+__global__ void k_zero_bytes(uint32_t *p, int64_t words) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
 // Sizes the piece arrays for the current adjacency capacities and
 // threshold: a row with at least split_min entries holds that many slots,
 // so at most adj_cap / split_min in-rows are long (with at most
@@ -1441,6 +1480,7 @@ template <typename T>
 int run_async(dfpr_graph *g, dfpr_stats *st) {
   hipStream_t s = g->stream;
   k_async_begin<<<1, 64, 0, s>>>(g->ctl);
+  k_list_groups<<<1, 256, 0, s>>>(g->gflags, g->ngroups, g->gwl, g->ctl);
   DFPR_HIP(hipGetLastError());
   RankArgs<T> A = make_args<T>(g, g->cur, g->cur);
   // grid from the groups listed by the marking (kChunksPerWave)
@@ -1502,6 +1542,10 @@ int finish_update(dfpr_graph *g) {
     k_cleanup_groups<<<grid_for((int64_t)glen, g->cu_count), 256, 0, s>>>(
         g->gflags, g->flags, g->gwl, glen, g->n);
   }
+  // the marking lists groups in both schemes; only the lock-free one
+  // builds and clears the group worklist
+  const int64_t gwords = ((int64_t)g->ngroups + 3) / 4;
+  k_zero_bytes<<<grid_for(gwords, g->cu_count), 256, 0, s>>>(g->gflags, gwords);
   k_reset_marks<<<1, 64, 0, s>>>(g->ctl);
   DFPR_HIP(hipGetLastError());
   g->pending_marks = 0;
@@ -1645,6 +1689,8 @@ int update_many_t(dfpr_graph *const *gs, int32_t count, dfpr_stats *stats) {
   DFPR_HIP(hipMemcpyAsync(d_desc, h.data(), dbytes, hipMemcpyHostToDevice, s));
   const int gb = grid_for(na, g0->cu_count);
   k_begin_many<T><<<gb, 256, 0, s>>>(d_desc, na, d_done);
+  k_list_groups_many<T><<<na < g0->cu_count * 8 ? na : g0->cu_count * 8, 256, 0, s>>>(d_desc,
+                                                                                        na);
   k_gather_summary<T><<<gb, 256, 0, s>>>(d_desc, na, d_sum);
   std::vector<Summary> hs(na);
   DFPR_HIP(hipMemcpyAsync(hs.data(), d_sum, sbytes, hipMemcpyDeviceToHost, s));
