@@ -18,8 +18,10 @@
 // Marking: for every source u with a real change, u itself (self-loop), its
 // current out-neighbours and the targets of its deleted edges -- together
 // (G^{t-1} union G^t).out(u) -- get the affected flag and their 256-vertex
-// group the listed flag; the vertices marked first are counted.  The
-// update builds its work lists from these flags.
+// group the listed flag, by plain byte stores (between updates a flag byte
+// only ever goes from 0 to set, so the stores need no atomics); the set
+// flags are counted afterwards.  The update builds its work lists from
+// these flags.
 // Rows of at least kLongApply entries are not left to one wavefront:
 // their deletions run in a second launch with a 1024-thread workgroup per
 // row (segment keys staged in LDS, block-wide compaction), and their
@@ -385,9 +387,8 @@ __global__ void k_mark_sources(int64_t S, const int64_t *segstart,
   const int lane = lane_id();
   const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  unsigned long long marked = 0;  // vertices this lane marked first
   auto mark = [&](bool act, int32_t v) {
-    if (act && mark_affected(flags, gflags, v).vnew) ++marked;
+    if (act) mark_plain(flags, gflags, v);
   };
   for (int64_t s = wave; s < S; s += nwaves) {
     const int64_t a = segstart[s], b = segstart[s + 1];
@@ -416,27 +417,40 @@ __global__ void k_mark_sources(int64_t S, const int64_t *segstart,
       mark(act, act ? (int32_t)((uk[e] >> 1) & 0x7FFFFFFFull) : -1);
     }
   }
-  marked = wave_sum(marked);
-  if (lane == 0 && marked) atomicAdd((unsigned long long *)&ctl->marked, marked);
 }
 
 // Out-rows deferred by k_mark_sources: every wavefront of the launch takes
 // its share of 64-entry chunks of every such row.
 __global__ void k_mark_long(const int32_t *long_list, AdjView out, uint32_t *flags,
-                            uint32_t *gflags, Ctl *ctl) {
+                            uint32_t *gflags, const Ctl *ctl) {
   const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t nt = (int64_t)gridDim.x * blockDim.x;
   const unsigned long long cnt = ctl->nlong_mark;
-  unsigned long long marked = 0;
   for (unsigned long long j = 0; j < cnt; ++j) {
     const int32_t u = long_list[j];
     const int64_t off = out.off[u];
     const int32_t deg = out.deg[u];
-    for (int64_t idx = t0; idx < deg; idx += nt)
-      if (mark_affected(flags, gflags, out.adj[off + idx]).vnew) ++marked;
+    for (int64_t idx = t0; idx < deg; idx += nt) mark_plain(flags, gflags, out.adj[off + idx]);
   }
-  marked = wave_sum(marked);
-  if (lane_id() == 0 && marked) atomicAdd((unsigned long long *)&ctl->marked, marked);
+}
+
+// Marked vertices (affected flag set) into ctl->marked: one atomic per
+// workgroup.
+__global__ void __launch_bounds__(256) k_count_marked(const uint32_t *flags, int64_t words,
+                                                      Ctl *ctl) {
+  __shared__ unsigned long long part[256 / kWave];
+  unsigned long long c = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words;
+       i += (int64_t)gridDim.x * blockDim.x)
+    c += __popc(flags[i] & 0x01010101u);
+  c = wave_sum(c);
+  if (lane_id() == 0) part[threadIdx.x / kWave] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) t += part[w];
+    if (t) atomicAdd((unsigned long long *)&ctl->marked, t);
+  }
 }
 
 }  // namespace
@@ -611,6 +625,11 @@ int apply_batch(dfpr_graph *g, int64_t nd, const int32_t *ds,
     DFPR_HIP(hipGetLastError());
     k_mark_long<<<cu > 0 ? 4 * cu : 1, 256, 0, s>>>((const int32_t *)ml, o, g->flags,
                                                    g->gflags, g->ctl);
+    DFPR_HIP(hipGetLastError());
+    // the count covers every batch applied since the last update
+    const int64_t words = ((int64_t)g->n + 3) / 4;
+    DFPR_HIP(hipMemsetAsync(&g->ctl->marked, 0, sizeof(long long), s));
+    k_count_marked<<<grid_for(words, cu), 256, 0, s>>>(g->flags, words, g->ctl);
     DFPR_HIP(hipGetLastError());
   }
   DFPR_HIP(hipMemcpyAsync(g->h_ctl, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));

@@ -302,8 +302,18 @@ __device__ __forceinline__ int wave_append(bool want, int32_t v,
 }
 
 // Marks v affected and lists its group.  vnew / gnew report whether v / its
-// group were new.  Coherent (agent-scope) pre-checks skip the atomics when
-// the bits are already set.
+// group were new (decided by the atomics).  The pre-checks skip the atomics
+// when the bits are already set: coherent (agent-scope) ones inside the
+// lock-free kernel, plain ones elsewhere, where a stale read only costs an
+// extra atomic.
+// Marks v affected and lists its group with plain byte stores: valid while
+// no other bit of these bytes changes concurrently (the marking phase
+// between updates, where a byte only goes from 0 to the flag).
+__device__ __forceinline__ void mark_plain(uint32_t *flags, uint32_t *gflags, int32_t v) {
+  reinterpret_cast<uint8_t *>(flags)[v] = (uint8_t)kVA;
+  reinterpret_cast<uint8_t *>(gflags)[v >> kGroupShift] = (uint8_t)kGA;
+}
+
 struct MarkOut {
   bool vnew;
   bool gnew;
@@ -311,10 +321,11 @@ struct MarkOut {
 };
 
 __device__ __forceinline__ MarkOut mark_affected(uint32_t *flags,
-                                                 uint32_t *gflags, int32_t v) {
+                                                 uint32_t *gflags, int32_t v,
+                                                 bool coherent = true) {
   MarkOut o{false, false, v >> kGroupShift};
-  if (!(flag_byte(flags, v, true) & kVA)) o.vnew = !(flag_set(flags, v, kVA) & kVA);
-  if (!(flag_byte(gflags, o.g, true) & kGA))
+  if (!(flag_byte(flags, v, coherent) & kVA)) o.vnew = !(flag_set(flags, v, kVA) & kVA);
+  if (!(flag_byte(gflags, o.g, coherent) & kGA))
     o.gnew = !(flag_set(gflags, o.g, kGA) & kGA);
   return o;
 }
