@@ -109,8 +109,14 @@ typedef struct {
   int32_t grid_blocks;   /* workgroups of the rank kernels; 0 = automatic:
                             barrier-based, at most 14 wavefronts per CU and
                             no more than an iteration's work items;
-                            lock-free, the co-resident workgroups, at most
-                            one wavefront per listed vertex group          */
+                            lock-free, about four claims per wavefront per
+                            sweep                                           */
+  int32_t graph_replay;  /* barrier-based loop: 0 one launch sequence per
+                            iteration from the host; 1 two iterations
+                            captured once in a HIP graph and replayed (kernel
+                            time is then reported for the whole loop);
+                            2 (default) replay when the graph has at most
+                            2^22 in-edge slots, where launches dominate    */
 } dfpr_params;
 
 typedef struct {

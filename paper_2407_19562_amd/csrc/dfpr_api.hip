@@ -67,6 +67,8 @@ int check_params(const dfpr_params *p) {
   if (p->reorder < 0 || p->reorder > 2) return fail(DFPR_EINVAL, "reorder must be 0, 1 or 2");
   if (p->grid_blocks < 0 || (int64_t)p->grid_blocks * (p->block_size / 64) > 32768)
     return fail(DFPR_EINVAL, "grid_blocks * waves per block must be <= 32768");
+  if (p->graph_replay < 0 || p->graph_replay > 2)
+    return fail(DFPR_EINVAL, "graph_replay must be 0, 1 or 2");
   return DFPR_OK;
 }
 
@@ -78,9 +80,9 @@ static void release(dfpr_graph *g) {
                   g->R[0],    g->R[1],    g->C[0],    g->C[1],
                   g->flags,   g->wl,      g->ctl,     g->sync_max,
                   g->sync_grab, g->sync_len, g->gflags, g->gwl,
-                  g->ext2int, g->int2ext, g->steps, g->epre,
+                  g->ext2int, g->int2ext, g->steps,
                   g->split.lrow, g->split.lpre, g->split.lcnt, g->split.prow,
-                  g->split.ppart, g->split.xrow};
+                  g->split.ppart, g->split.xrow, g->tiles};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (auto &s : g->scratch)
@@ -90,6 +92,10 @@ static void release(dfpr_graph *g) {
     if (e) (void)hipEventDestroy(e);
   for (auto &e : g->iter_ev)
     if (e) (void)hipEventDestroy(e);
+  for (auto &row : g->replay)
+    for (auto &x : row)
+      if (x) (void)hipGraphExecDestroy(x);
+  if (g->capture_stream) (void)hipStreamDestroy(g->capture_stream);
   delete g;
 }
 
@@ -109,7 +115,8 @@ static int alloc_graph(dfpr_graph *g) {
   DFPR_HIP(hipMalloc(&g->flags, fbytes));
   DFPR_HIP(hipMemsetAsync(g->flags, 0, fbytes, g->stream));
   DFPR_HIP(hipMalloc(&g->steps, (n + 1) * 4));
-  DFPR_HIP(hipMalloc(&g->epre, n * 8));
+  DFPR_HIP(hipMalloc(&g->tiles, 2 * (n / 256 + 2) * 16));
+  DFPR_HIP(hipMemsetAsync(g->tiles, 0, 2 * (n / 256 + 2) * 16, g->stream));
   DFPR_HIP(hipMalloc(&g->wl, n * 4));
   DFPR_HIP(hipMemsetAsync(g->wl, 0xFF, n * 4, g->stream));
   g->ngroups = (int32_t)((n + kGroup - 1) / kGroup);
@@ -172,6 +179,7 @@ int dfpr_params_default(dfpr_params *p) {
   p->renormalize = 0;
   p->timeout_ms = 60000;
   p->grid_blocks = 0;
+  p->graph_replay = 2;
   return DFPR_OK;
 }
 

@@ -98,7 +98,7 @@ struct Ctl {
   int sync_done;                   // synchronous iteration finished
   int sync_final;                  // iterations made by the synchronous loop
   int sync_conv;                   // synchronous loop met the tolerance
-  int pad;
+  int iter;                        // barrier-based iteration in progress
   double sum;                      // fp64 rank sum (renormalisation)
 };
 
@@ -160,7 +160,14 @@ struct dfpr_graph {
   uint32_t *gflags = nullptr;  // [ngroups] bytes
   int32_t *gwl = nullptr;      // group worklist [ngroups], unused slots -1
   int32_t *steps = nullptr;    // step starts over the worklist [n + 1]
-  int64_t *epre = nullptr;     // edge prefix over the worklist [n]
+  void *tiles = nullptr;       // per-tile sums and their prefixes
+                               // [2 * (n / 256 + 2)] x 16 bytes
+  // barrier-based loop replayed from HIP graphs: per (scheme, parity of
+  // the current rank buffer) an instantiated two-iteration graph and the
+  // hash of the arguments it was captured with
+  hipGraphExec_t replay[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  uint64_t replay_key[2][2] = {{0, 0}, {0, 0}};
+  hipStream_t capture_stream = nullptr;
   dfpr::Split split;           // rows gathered in pieces
   int32_t *ext2int = nullptr;  // caller id -> internal id (null: identity)
   int32_t *int2ext = nullptr;  // internal id -> caller id

@@ -666,9 +666,9 @@ __global__ void __launch_bounds__(256) k_df_async_many(const RankArgs<T> *descs,
 // worklist (all vertices for static) is cut into steps of at most 256
 // entries and about kStepEdges in-edges, and wavefronts claim steps.
 template <typename T, int MODE>
-__global__ void __launch_bounds__(256) k_sync_iter(RankArgs<T> A, int iter,
-                                                   const int32_t *steps) {
+__global__ void __launch_bounds__(256) k_sync_iter(RankArgs<T> A, const int32_t *steps) {
   if (A.ctl->sync_done) return;
+  const int iter = A.ctl->iter;  // device-side, so a captured launch replays
   WaveLds<T> &L = wave_lds<T>();
   const int lane = lane_id();
   Counters cnt;
@@ -771,7 +771,7 @@ __global__ void __launch_bounds__(256) k_expand_long(const int32_t *xrow,
 // convergence decision, and the slot words reset for the next iteration.
 __global__ void k_sync_finish(Ctl *ctl, unsigned long long *sync_max,
                               unsigned long long *sync_len,
-                              unsigned long long *slots, int iter,
+                              unsigned long long *slots,
                               double tol, int max_iters, int df) {
   const int t = threadIdx.x;
   unsigned long long bits = 0;
@@ -787,6 +787,7 @@ __global__ void k_sync_finish(Ctl *ctl, unsigned long long *sync_max,
   if (t != 0) return;
   ctl->nexp = 0;
   if (ctl->sync_done) return;
+  const int iter = ctl->iter;
   sync_max[iter] = bits;
   const double md = __longlong_as_double((long long)bits);
   if (md <= tol || iter + 1 >= max_iters) {
@@ -795,6 +796,7 @@ __global__ void k_sync_finish(Ctl *ctl, unsigned long long *sync_max,
     ctl->sync_conv = md <= tol ? 1 : 0;
   } else {
     sync_len[iter + 1] = ctl->nsteps | (ctl->npieces << 32);
+    ctl->iter = iter + 1;
   }
 }
 
@@ -812,6 +814,7 @@ __global__ void k_sync_begin(Ctl *ctl, unsigned long long *sync_max,
     ctl->sync_done = 0;
     ctl->sync_final = 0;
     ctl->sync_conv = 0;
+    ctl->iter = 0;
     ctl->vertices = ctl->edges = ctl->out_scanned = 0;
     ctl->abort = 0;
     ctl->newly = 0;
@@ -1067,6 +1070,7 @@ inline long long async_waves(long long chunks, int cu_count) {
 template <typename T>
 RankArgs<T> make_args(dfpr_graph *g, int rd, int wr) {
   RankArgs<T> A;
+  std::memset(&A, 0, sizeof(A));  // padding included: the args are hashed
   A.n = g->n;
   A.in_off = g->in.off;
   A.in_deg = g->in.deg;
@@ -1335,22 +1339,50 @@ int ensure_split(dfpr_graph *g) {
   return DFPR_OK;
 }
 
-// Builds the work items of the next barrier-based iteration (all = true:
-// every vertex, static PageRank).  reuse: the previous items stay when the
-// last iteration affected no new vertex (decided on the device).
-int build_items(dfpr_graph *g, bool all, bool reuse) {
-  hipStream_t s = g->stream;
-  if (g->n == 0) {
-    DFPR_HIP(hipMemsetAsync(&g->ctl->tail, 0, 4 * sizeof(unsigned long long), s));
-    return DFPR_OK;
+// Exclusive scan of nt1 tile sums by one workgroup (whole wavefronts, at
+// most 16): each thread sums a contiguous run, the run totals are scanned
+// across the workgroup, and each thread writes its run's prefixes.
+__global__ void __launch_bounds__(1024) k_tile_scan(const TileSum *sums, TileSum *pre,
+                                                    int32_t nt1,
+                                                    const unsigned long long *slots,
+                                                    int reuse) {
+  if (reuse && slots_newly(slots) == 0) return;
+  __shared__ int32_t wtot[4][1024 / kWave];
+  const int lane = lane_id();
+  const int w = threadIdx.x / kWave;
+  const int32_t per = (nt1 + (int32_t)blockDim.x - 1) / (int32_t)blockDim.x;
+  const int32_t b = (int32_t)threadIdx.x * per;
+  const int32_t e = b + per < nt1 ? b + per : nt1;
+  TileSum t{0, 0, 0, 0};
+  for (int32_t i = b; i < e; ++i) t = TileSumPlus()(t, sums[i]);
+  int32_t v[4] = {t.sel, t.steps, t.nlong, t.pieces};
+  int32_t ex[4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    const int32_t incl = wave_incl_scan(v[f]);
+    if (lane == kWave - 1) wtot[f][w] = incl;
+    ex[f] = incl - v[f];
   }
+  __syncthreads();
+#pragma unroll
+  for (int f = 0; f < 4; ++f)
+    for (int i = 0; i < w; ++i) ex[f] += wtot[f][i];
+  TileSum run{ex[0], ex[1], ex[2], ex[3]};
+  for (int32_t i = b; i < e; ++i) {
+    pre[i] = run;
+    run = TileSumPlus()(run, sums[i]);
+  }
+}
+
+// Launches the three steps that build the work items of the next
+// barrier-based iteration (all = true: every vertex, static PageRank) on
+// stream s; no host synchronisation, so the launches can be captured.
+// reuse: the previous items stay when the last iteration affected no new
+// vertex (decided on the device).
+void launch_items(dfpr_graph *g, bool all, bool reuse, hipStream_t s) {
   const int32_t nt = (g->n + kRows - 1) / kRows;
-  const size_t tbytes = sizeof(TileSum) * ((size_t)nt + 1);
-  void *buf = nullptr;
-  int rc = scratch_get(g, 15, 2 * tbytes, &buf);
-  if (rc) return rc;
-  TileSum *sums = (TileSum *)buf;
-  TileSum *pre = (TileSum *)((char *)buf + tbytes);
+  TileSum *sums = (TileSum *)g->tiles;
+  TileSum *pre = sums + (nt + 1);
   const uint8_t *fl = reinterpret_cast<const uint8_t *>(g->flags);
   const int32_t split = g->p.split_min_degree;
   if (all)
@@ -1358,22 +1390,82 @@ int build_items(dfpr_graph *g, bool all, bool reuse) {
   else
     k_tile_count<false><<<nt, 256, 0, s>>>(fl, g->in.deg, g->n, split, sums,
                                            g->sync_grab, reuse);
-  DFPR_HIP(hipGetLastError());
-  size_t tb = 0;
-  const TileSum zero{0, 0, 0, 0};
-  DFPR_HIP(rocprim::exclusive_scan(nullptr, tb, sums, pre, zero, (size_t)nt + 1,
-                                   TileSumPlus(), s));
-  void *tmp = nullptr;
-  if ((rc = scratch_get(g, 14, tb, &tmp))) return rc;
-  DFPR_HIP(rocprim::exclusive_scan(tmp, tb, sums, pre, zero, (size_t)nt + 1,
-                                   TileSumPlus(), s));
+  k_tile_scan<<<1, 1024, 0, s>>>(sums, pre, nt + 1, g->sync_grab, all ? 0 : reuse);
   if (all)
     k_tile_emit<true><<<nt, 256, 0, s>>>(fl, g->in.deg, g->n, split, pre, g->wl, g->steps,
                                          g->split, g->ctl, g->sync_grab, 0);
   else
     k_tile_emit<false><<<nt, 256, 0, s>>>(fl, g->in.deg, g->n, split, pre, g->wl, g->steps,
                                           g->split, g->ctl, g->sync_grab, reuse);
+}
+
+// Builds the work items of the next barrier-based iteration on the graph's
+// stream (see launch_items).
+int build_items(dfpr_graph *g, bool all, bool reuse) {
+  launch_items(g, all, reuse, g->stream);
   DFPR_HIP(hipGetLastError());
+  return DFPR_OK;
+}
+
+inline uint64_t fnv1a(uint64_t h, const void *p, size_t n) {
+  const unsigned char *b = static_cast<const unsigned char *>(p);
+  for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+  return h;
+}
+
+// The instantiated two-iteration graph for the scheme and the current rank
+// parity, captured again whenever an argument of its launches changed
+// (buffers regrown, parameters set).  Capture runs on a private stream; the
+// graph is launched on the graph's own stream.
+template <typename T, typename F>
+int replay_graph(dfpr_graph *g, int mode, int blocks, size_t lds, F &launch_iteration,
+                 hipGraphExec_t *out) {
+  const int m = mode == kAll ? 1 : 0;
+  const int par = g->cur & 1;
+  uint64_t key = 1469598103934665603ull;
+  for (int k = 0; k < 2; ++k) {
+    RankArgs<T> A = make_args<T>(g, par ^ k, par ^ k ^ 1);
+    key = fnv1a(key, &A, sizeof(A));
+  }
+  const void *ptrs[] = {g->steps, g->tiles, g->wl, g->flags, g->ctl, g->sync_grab,
+                        g->sync_max, g->sync_len, g->split.xrow, g->out.off,
+                        g->out.deg, g->out.adj, g->in.deg};
+  key = fnv1a(key, ptrs, sizeof(ptrs));
+  const int64_t vals[] = {blocks, (int64_t)lds, g->p.block_size, g->p.split_min_degree,
+                          g->p.max_iters, g->n, g->cu_count, (int64_t)sizeof(T)};
+  key = fnv1a(key, vals, sizeof(vals));
+  double tol = g->p.tol;
+  key = fnv1a(key, &tol, sizeof(tol));
+  if (g->replay[m][par] && g->replay_key[m][par] == key) {
+    *out = g->replay[m][par];
+    return DFPR_OK;
+  }
+  if (g->replay[m][par]) {
+    DFPR_HIP(hipGraphExecDestroy(g->replay[m][par]));
+    g->replay[m][par] = nullptr;
+  }
+  if (!g->capture_stream)
+    DFPR_HIP(hipStreamCreateWithFlags(&g->capture_stream, hipStreamNonBlocking));
+  hipStream_t cs = g->capture_stream;
+  DFPR_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  launch_iteration(par, cs, nullptr, nullptr);
+  launch_iteration(par ^ 1, cs, nullptr, nullptr);
+  hipGraph_t graph = nullptr;
+  const hipError_t e1 = hipStreamEndCapture(cs, &graph);
+  const hipError_t e0 = hipGetLastError();
+  if (e1 != hipSuccess || e0 != hipSuccess || !graph) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return fail(DFPR_EHIP, std::string("graph capture: ") +
+                               hipGetErrorString(e1 != hipSuccess ? e1 : e0));
+  }
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e2 != hipSuccess) return fail(DFPR_EHIP, std::string("graph instantiate: ") +
+                                                   hipGetErrorString(e2));
+  g->replay[m][par] = exec;
+  g->replay_key[m][par] = key;
+  *out = exec;
   return DFPR_OK;
 }
 
@@ -1412,32 +1504,56 @@ int run_sync(dfpr_graph *g, int mode, dfpr_stats *st) {
     if (want < blocks) blocks = (int)want;
   }
   const int xgrid = g->cu_count > 0 ? g->cu_count : 1;
-  while ((int)g->iter_ev.size() < 2 * iters) {
-    hipEvent_t e = nullptr;
-    DFPR_HIP(hipEventCreate(&e));
-    g->iter_ev.push_back(e);
+  const int poll = 8;
+  // one iteration's launches on stream q: rank kernel, deferred out-rows,
+  // next items, convergence decision (iteration index on the device)
+  auto launch_iteration = [&](int parity, hipStream_t q, hipEvent_t e0, hipEvent_t e1) {
+    RankArgs<T> A = make_args<T>(g, parity, parity ^ 1);
+    if (e0) (void)hipEventRecord(e0, q);
+    kern<<<blocks, g->p.block_size, lds, q>>>(A, g->steps);
+    if (e1) (void)hipEventRecord(e1, q);
+    if (mode != kAll) {
+      k_expand_long<<<xgrid, 256, 0, q>>>(g->split.xrow, g->out.off, g->out.deg,
+                                          g->out.adj, g->flags, g->ctl, g->sync_grab);
+      launch_items(g, false, true, q);
+    }
+    k_sync_finish<<<1, 64, 0, q>>>(g->ctl, g->sync_max, g->sync_len, g->sync_grab,
+                                   g->p.tol, iters, mode == kSyncDF);
+  };
+  const bool replay = g->p.graph_replay == 1 ||
+                      (g->p.graph_replay == 2 && g->in.adj_cap <= (int64_t(1) << 22));
+  hipGraphExec_t exec = nullptr;
+  if (replay) {
+    int rc = replay_graph<T>(g, mode, blocks, lds, launch_iteration, &exec);
+    if (rc) return rc;
+  } else {
+    while ((int)g->iter_ev.size() < 2 * iters) {
+      hipEvent_t e = nullptr;
+      DFPR_HIP(hipEventCreate(&e));
+      g->iter_ev.push_back(e);
+    }
   }
   DFPR_HIP(hipEventRecord(g->ev[1], s));
-  const int poll = 8;
   int it = 0;
-  for (; it < iters; ++it) {
-    RankArgs<T> A = make_args<T>(g, (g->cur + it) & 1, (g->cur + it + 1) & 1);
-    DFPR_HIP(hipEventRecord(g->iter_ev[2 * it], s));
-    kern<<<blocks, g->p.block_size, lds, s>>>(A, it, g->steps);
-    DFPR_HIP(hipEventRecord(g->iter_ev[2 * it + 1], s));
-    if (mode != kAll) {
-      k_expand_long<<<xgrid, 256, 0, s>>>(g->split.xrow, g->out.off, g->out.deg,
-                                          g->out.adj, g->flags, g->ctl, g->sync_grab);
-      int rc = build_items(g, false, true);
-      if (rc) return rc;
+  if (exec) {
+    // two iterations per replay, the host polls every `poll` iterations
+    for (; it < iters; it += 2) {
+      DFPR_HIP(hipGraphLaunch(exec, s));
+      if ((it + 2) % poll == 0 || it + 2 >= iters) {
+        DFPR_HIP(hipMemcpyAsync(g->h_ctl, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        DFPR_HIP(hipStreamSynchronize(s));
+        if (g->h_ctl->sync_done) break;
+      }
     }
-    k_sync_finish<<<1, 64, 0, s>>>(g->ctl, g->sync_max, g->sync_len, g->sync_grab, it,
-                                   g->p.tol, iters, mode == kSyncDF);
-    if ((it + 1) % poll == 0 || it + 1 == iters) {
-      DFPR_HIP(hipGetLastError());
-      DFPR_HIP(hipMemcpyAsync(g->h_ctl, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-      DFPR_HIP(hipStreamSynchronize(s));
-      if (g->h_ctl->sync_done) break;
+  } else {
+    for (; it < iters; ++it) {
+      launch_iteration((g->cur + it) & 1, s, g->iter_ev[2 * it], g->iter_ev[2 * it + 1]);
+      if ((it + 1) % poll == 0 || it + 1 == iters) {
+        DFPR_HIP(hipGetLastError());
+        DFPR_HIP(hipMemcpyAsync(g->h_ctl, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        DFPR_HIP(hipStreamSynchronize(s));
+        if (g->h_ctl->sync_done) break;
+      }
     }
   }
   DFPR_HIP(hipEventRecord(g->ev[2], s));
@@ -1464,12 +1580,17 @@ int run_sync(dfpr_graph *g, int mode, dfpr_stats *st) {
     st->out_edges_scanned = (int64_t)h.out_scanned;
     st->max_delta = md;
     // the iteration kernels alone (the item building between them is not
-    // included); iterations after the last one exit at once
+    // included); iterations after the last one exit at once.  Replayed
+    // loops: the whole loop.
     float ms = 0.f;
-    for (int i = 0; i < final_it; ++i) {
-      float x = 0.f;
-      (void)hipEventElapsedTime(&x, g->iter_ev[2 * i], g->iter_ev[2 * i + 1]);
-      ms += x;
+    if (exec) {
+      (void)hipEventElapsedTime(&ms, g->ev[1], g->ev[2]);
+    } else {
+      for (int i = 0; i < final_it; ++i) {
+        float x = 0.f;
+        (void)hipEventElapsedTime(&x, g->iter_ev[2 * i], g->iter_ev[2 * i + 1]);
+        ms += x;
+      }
     }
     st->ms_kernel = ms;
   }

@@ -51,7 +51,7 @@ class dfpr_params(ctypes.Structure):
                 ("split_min_degree", ctypes.c_int32), ("chunk", ctypes.c_int32),
                 ("block_size", ctypes.c_int32), ("reorder", ctypes.c_int32),
                 ("renormalize", ctypes.c_int32), ("timeout_ms", ctypes.c_int32),
-                ("grid_blocks", ctypes.c_int32)]
+                ("grid_blocks", ctypes.c_int32), ("graph_replay", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -91,7 +91,8 @@ def test_strerror_and_bad_params(lib):
     ("chunk", 32), ("chunk", 100), ("chunk", 8192), ("block_size", 96),
     ("block_size", 512), ("reorder", 3), ("split_min_degree", 0),
     ("kahan_min_degree", -1), ("max_iters", 0), ("max_iters", 9000),
-    ("precision", 16), ("grid_blocks", 1 << 20), ("timeout_ms", -5)])
+    ("precision", 16), ("grid_blocks", 1 << 20), ("timeout_ms", -5),
+    ("graph_replay", 3)])
 def test_invalid_parameters_are_rejected_before_any_device_call(lib, field, value):
     h = lib._lib()
     out = ctypes.c_void_p()

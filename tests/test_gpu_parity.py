@@ -314,6 +314,40 @@ def test_sync_update_is_deterministic(D, O):
     assert np.array_equal(out[0], out[1])
 
 
+@pytest.mark.parametrize("kind", ["rmat_small", "heavy_rows"])
+def test_graph_replay_matches_launches(D, O, kind):
+    # the barrier-based loop replayed from a captured HIP graph gives the
+    # same bits as launching it iteration by iteration, for several updates
+    # in a row on the same graph objects (eager applies between replays, one
+    # relocating a hub row; a parameter change forcing a new capture), and
+    # static PageRank likewise; both match the oracle
+    say("graph replay", kind)
+    n, s, d = getattr(inputs, kind)()
+    bs = inputs.batches(n, s, d, 3, seed=55, frac=2e-3)
+    hub = np.zeros(3000, np.int32) + 7
+    grow = inputs.Batch(np.empty(0, np.int32), np.empty(0, np.int32), hub,
+                        np.arange(100, 3100, dtype=np.int32))
+    cs, cd = s, d
+    with graph(D, n, s, d, mode=D.DFPR_SYNC, graph_replay=1) as gr, \
+         graph(D, n, s, d, mode=D.DFPR_SYNC, graph_replay=0) as ge:
+        for g in (gr, ge):
+            rc, st = g.static()
+            assert rc == D.DFPR_OK
+        assert np.array_equal(gr.ranks(), ge.ranks())
+        for k, b in enumerate([bs[0], grow, bs[1], bs[2]]):
+            cs, cd, _, _ = O.apply_batch(n, cs, cd, b.del_src, b.del_dst, b.ins_src, b.ins_dst)
+            for g in (gr, ge):
+                if k == 2:
+                    g.set_params(split_min_degree=256)
+                g.apply(b)
+                rc, st = g.update()
+                assert rc == D.DFPR_OK
+            Rr, Re = gr.ranks(), ge.ranks()
+            assert np.array_equal(Rr, Re), k
+        ref, _, _ = O.pagerank(n, cs, cd)
+        assert err64(Rr, ref) < FP64_TOL
+
+
 @pytest.mark.parametrize("mode", ["sync", "async"])
 def test_df_fp32_matches_oracle(D, O, mode):
     say("df fp32", mode)
