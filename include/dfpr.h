@@ -171,6 +171,19 @@ int dfpr_static(dfpr_graph *g, dfpr_stats *stats);
  * vertex, started from the current ranks. */
 int dfpr_naive_dynamic(dfpr_graph *g, dfpr_stats *stats);
 
+/* Lock-free static and naive-dynamic PageRank (Algorithms 4 and 6,
+ * Section 3.5.1): every vertex is recomputed in place by the persistent
+ * kernel of the lock-free scheme, from 1/n (static) or from the current
+ * ranks (naive-dynamic), until a full sweep moves no vertex by more than
+ * frontier_tol (stricter than the tol at which those algorithms clear R_C:
+ * with tol alone a hub with 25000 in-edges ended 1.04e-9 from the fixed
+ * point), or max_iters sweeps.
+ * Batches applied before the call count as served (their marks are
+ * cleared).  Returns DFPR_NOTCONVERGED at the cap, DFPR_EABORT if the
+ * watchdog fired. */
+int dfpr_static_lock_free(dfpr_graph *g, dfpr_stats *stats);
+int dfpr_naive_dynamic_lock_free(dfpr_graph *g, dfpr_stats *stats);
+
 /* Overwrites the ranks with r[n] (fp64; rounded for fp32 graphs). */
 int dfpr_set_ranks(dfpr_graph *g, const double *r, int mem);
 

@@ -287,6 +287,18 @@ int dfpr_naive_dynamic(dfpr_graph *g, dfpr_stats *stats) {
   return run_rank(g, 1, stats);
 }
 
+int dfpr_static_lock_free(dfpr_graph *g, dfpr_stats *stats) {
+  if (!g) return fail(DFPR_EINVAL, "graph is NULL");
+  if (stats) *stats = dfpr_stats{};
+  return run_rank(g, 3, stats);
+}
+
+int dfpr_naive_dynamic_lock_free(dfpr_graph *g, dfpr_stats *stats) {
+  if (!g) return fail(DFPR_EINVAL, "graph is NULL");
+  if (stats) *stats = dfpr_stats{};
+  return run_rank(g, 4, stats);
+}
+
 int dfpr_update(dfpr_graph *g, dfpr_stats *stats) {
   if (!g) return fail(DFPR_EINVAL, "graph is NULL");
   if (stats) *stats = dfpr_stats{};

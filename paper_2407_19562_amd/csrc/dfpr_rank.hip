@@ -1597,10 +1597,37 @@ int run_sync(dfpr_graph *g, int mode, dfpr_stats *st) {
   return h.sync_conv ? DFPR_OK : DFPR_NOTCONVERGED;
 }
 
+// Every vertex affected, with its out-row counted as marked (nothing to
+// expand) and every group listed: the lock-free static and naive-dynamic
+// runs.
+__global__ void k_mark_all(uint32_t *flags, int64_t fwords, uint32_t *gflags,
+                           int64_t gwords) {
+  const uint32_t fv = (kVA | kEX) * 0x01010101u;
+  const uint32_t gv = kGA * 0x01010101u;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < fwords;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    flags[i] = fv;
+    if (i < gwords) gflags[i] = gv;
+  }
+}
+
+// all: every vertex is affected (lock-free static / naive-dynamic,
+// Algorithms 4 and 6).  Otherwise the DF update of the pending marks
+// (Algorithm 2).  Either way the launch ends after a full sweep in which
+// no vertex moved by more than the frontier tolerance.
 template <typename T>
-int run_async(dfpr_graph *g, dfpr_stats *st) {
+int run_async(dfpr_graph *g, dfpr_stats *st, bool all = false) {
   hipStream_t s = g->stream;
   k_async_begin<<<1, 64, 0, s>>>(g->ctl);
+  if (all) {
+    // flag bytes past n in the last word and group bytes past the last
+    // group stay harmless: no kernel reads a flag of an id >= n, and the
+    // group list is built from the first ngroups bytes only
+    const int64_t fwords = ((int64_t)g->n + 3) / 4;
+    const int64_t gwords = ((int64_t)g->ngroups + 3) / 4;
+    k_mark_all<<<grid_for(fwords, g->cu_count), 256, 0, s>>>(g->flags, fwords, g->gflags,
+                                                             gwords);
+  }
   k_list_groups<<<1, 256, 0, s>>>(g->gflags, g->ngroups, g->gwl, g->ctl);
   DFPR_HIP(hipGetLastError());
   RankArgs<T> A = make_args<T>(g, g->cur, g->cur);
@@ -1734,6 +1761,19 @@ int run_rank(dfpr_graph *g, int kind, dfpr_stats *st) {
       if (rc) return rc;
     }
     rc = g->elem == 8 ? run_sync<double>(g, kAll, st) : run_sync<float>(g, kAll, st);
+  } else if (kind == 3 || kind == 4) {  // the same, lock-free
+    if (kind == 3) {
+      rc = init_uniform_ranks(g);
+      if (rc) return rc;
+    }
+    rc = g->elem == 8 ? run_async<double>(g, st, true) : run_async<float>(g, st, true);
+    if (st) {
+      st->initial_marked = g->n;
+      st->affected = g->n;
+    }
+    // every vertex was recomputed: batches applied before are served too
+    int rc2 = finish_update(g);
+    if (rc2) return rc2;
   } else {
     if (g->pending_marks == 0) {
       // nothing affected: ranks stay bit-identical

@@ -36,7 +36,8 @@ DFPR_IN = 1
 EXPORTS = (
     "dfpr_params_default", "dfpr_graph_create", "dfpr_graph_destroy",
     "dfpr_set_params", "dfpr_get_params", "dfpr_graph_size", "dfpr_static",
-    "dfpr_naive_dynamic", "dfpr_set_ranks", "dfpr_read_ranks",
+    "dfpr_naive_dynamic", "dfpr_static_lock_free", "dfpr_naive_dynamic_lock_free",
+    "dfpr_set_ranks", "dfpr_read_ranks",
     "dfpr_apply_batch", "dfpr_update", "dfpr_update_many", "dfpr_read_edges",
     "dfpr_read_marks", "dfpr_graph_bytes", "dfpr_stream_copy",
     "dfpr_last_kernel_bytes", "dfpr_strerror", "dfpr_last_error",
@@ -102,6 +103,8 @@ def _lib():
             "dfpr_graph_size": [V, P(i32), P(i64)],
             "dfpr_static": [V, P(dfpr_stats)],
             "dfpr_naive_dynamic": [V, P(dfpr_stats)],
+            "dfpr_static_lock_free": [V, P(dfpr_stats)],
+            "dfpr_naive_dynamic_lock_free": [V, P(dfpr_stats)],
             "dfpr_set_ranks": [V, V, ctypes.c_int],
             "dfpr_read_ranks": [V, V, ctypes.c_int],
             "dfpr_apply_batch": [V, i64, V, V, i64, V, V, ctypes.c_int,
@@ -225,6 +228,15 @@ def dfpr_static(g):
 
 def dfpr_naive_dynamic(g):
     return _stats_call(_lib().dfpr_naive_dynamic, g, "dfpr_naive_dynamic")
+
+
+def dfpr_static_lock_free(g):
+    return _stats_call(_lib().dfpr_static_lock_free, g, "dfpr_static_lock_free")
+
+
+def dfpr_naive_dynamic_lock_free(g):
+    return _stats_call(_lib().dfpr_naive_dynamic_lock_free, g,
+                       "dfpr_naive_dynamic_lock_free")
 
 
 def dfpr_update(g):
@@ -375,6 +387,12 @@ class Graph:
 
     def naive_dynamic(self):
         return dfpr_naive_dynamic(self.h)
+
+    def static_lock_free(self):
+        return dfpr_static_lock_free(self.h)
+
+    def naive_dynamic_lock_free(self):
+        return dfpr_naive_dynamic_lock_free(self.h)
 
     def apply_batch(self, del_src, del_dst, ins_src, ins_dst):
         return dfpr_apply_batch(self.h, del_src, del_dst, ins_src, ins_dst)

@@ -235,18 +235,20 @@ def test_static_matches_oracle(D, O, prec):
         assert rel32(R, ref) < FP32_REL
 
 
-@pytest.mark.parametrize("reorder", [0, 2])
+@pytest.mark.parametrize("kind,reorder", [("rmat_small", 0), ("rmat_small", 2),
+                                          ("heavy_rows", 0)])
 @pytest.mark.parametrize("mode", ["sync", "async"])
 @pytest.mark.parametrize("frac", [1e-3, 1e-2])
-def test_df_fp64_matches_oracle(D, O, mode, frac, reorder):
-    say("df fp64", mode, frac, reorder)
-    n, s, d = inputs.rmat_small()
+def test_df_fp64_matches_oracle(D, O, mode, frac, kind, reorder):
+    say("df fp64", kind, mode, frac, reorder)
+    n, s, d = getattr(inputs, kind)()
     R0, _, _ = O.pagerank(n, s, d)
     b = inputs.batches(n, s, d, 1, 1001, frac=frac)[0]
     ns, nd, res, ndel, nins = O.update(n, s, d, b, R0)
     ref, _, _ = O.pagerank(n, ns, nd)
     m = D.DFPR_SYNC if mode == "sync" else D.DFPR_ASYNC
-    with graph(D, n, s, d, mode=m, reorder=reorder) as g:
+    cap = 4000 if (kind == "heavy_rows" and mode == "async") else 500
+    with graph(D, n, s, d, mode=m, reorder=reorder, max_iters=cap) as g:
         g.set_ranks(R0)                        # parity mode: R^{t-1} exact
         assert g.apply(b) == (ndel, nins)
         rc, st = g.update()
@@ -459,6 +461,41 @@ def test_df_ragged_small_graphs(D, O):
                     assert rc == D.DFPR_OK
                     ref, _, _ = O.pagerank(n, ns, nd)
                     assert err64(g.ranks(), ref) < FP64_TOL
+
+
+@pytest.mark.parametrize("kind", ["rmat_small", "heavy_rows"])
+@pytest.mark.parametrize("prec", [64, 32])
+def test_lock_free_static_and_naive_dynamic(D, O, kind, prec):
+    # Algorithms 4 and 6 on the persistent kernel: a full sweep with no
+    # change above the frontier tolerance ends the launch.  A sweep is one
+    # pass of the claim cursor; with hub groups far slower than the rest
+    # (heavy_rows) the cursor passes several times while a hub group is
+    # recomputed, so that graph gets a larger sweep cap
+    say("lock-free static / ND", kind, prec)
+    n, s, d = getattr(inputs, kind)()
+    R0, _, _ = O.pagerank(n, s, d)
+    b = inputs.batches(n, s, d, 1, 61, frac=1e-2)[0]
+    ns, nd, _, _ = O.apply_batch(n, s, d, b.del_src, b.del_dst, b.ins_src, b.ins_dst)
+    R1, _, _ = O.pagerank(n, ns, nd)
+    cap = 4000 if kind == "heavy_rows" else 500
+    with graph(D, n, s, d, mode=D.DFPR_ASYNC, precision=prec, max_iters=cap,
+               renormalize=int(prec == 32)) as g:
+        rc, st = g.static_lock_free()
+        assert rc == D.DFPR_OK and st.converged and st.affected == n
+        Rs = g.ranks()
+        g.apply(b)
+        rc, st = g.naive_dynamic_lock_free()
+        assert rc == D.DFPR_OK and st.converged
+        Rn = g.ranks()
+        aff, cnt = g.marks()
+        assert cnt == 0 and not aff.any()       # the batch counts as served
+        rc, st = g.update()
+        assert rc == D.DFPR_OK and st.vertices_processed == 0
+    say("  static err", err64(Rs, R0), "nd err", err64(Rn, R1))
+    if prec == 64:
+        assert err64(Rs, R0) < FP64_TOL and err64(Rn, R1) < FP64_TOL
+    else:
+        assert rel32(Rs, R0) < FP32_REL and rel32(Rn, R1) < FP32_REL
 
 
 def test_naive_dynamic_matches_oracle(D, O):
