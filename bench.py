@@ -11,7 +11,8 @@ Other workloads (one JSON line each): `sweep` (batch sizes 1e-7..1e-1 |E|
 on the same R-MAT, DF vs static recompute, fp64 and fp32), `grid4096`
 (4096x4096 road-like grid, lock-free vs synchronous, fp64 and fp32),
 `batched1024` (1024 small graphs in one launch vs one by one), `serving`
-(resident graphs under a Poisson stream of batches), `rmat14` (small R-MAT).
+(resident graphs under a Poisson stream of batches), `rmat14` (small R-MAT),
+`faults` (delayed or stopped workgroups, barrier-based vs lock-free).
 """
 from __future__ import annotations
 
@@ -47,7 +48,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat22",
                     choices=["rmat22", "rmat14", "sweep", "grid4096",
-                             "batched1024", "serving"])
+                             "batched1024", "serving", "faults"])
     ap.add_argument("--frac", type=float, default=1e-3)
     ap.add_argument("--precision", type=int, default=64, choices=[32, 64])
     ap.add_argument("--mode", default="sync", choices=["async", "sync"])
@@ -336,6 +337,36 @@ def grid(args, torch, dfpr, inputs):
             "results": out}
 
 
+def faults(args, torch, dfpr, inputs):
+    """Fault simulation on the 2^22 R-MAT (DF, fp64, 1e-3 batches): a share
+    of the rank kernels' workgroups sleeps after every claim, or stops at a
+    claim boundary; barrier-based vs lock-free update time."""
+    n, s, d, desc = load_workload("rmat22")
+    bs = inputs.batches(n, s, d, 3, seed=batch_seed("rmat22", 1e-3), frac=1e-3)
+    dev = device_batches(torch, bs)
+    ds, dd = torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda()
+    ov = overrides(args)
+    cases = {"none": [0], "delay_100us_1pct": [100] + [0] * 99,
+             "delay_100us_10pct": [100] + [0] * 9, "stop_25pct": [-1, 0, 0, 0]}
+    out = {}
+    for mode in ("sync", "async"):
+        for name, table in cases.items():
+            g = dfpr.Graph(n, ds, dd, mode=MODES[mode], **ov)
+            g.static()
+            g.set_faults(table)
+            rec, total_s = run_steps(g, dev, 0, len(dev), torch)
+            g.close()
+            sm = summarize(rec)
+            out[f"{mode}_{name}"] = {"update_ms_mean": sm["latency_ms"]["mean"],
+                                     "sweeps_mean": sm["sweeps_mean"]}
+            log(f"{mode} {name}: {out[f'{mode}_{name}']}")
+    return {"metric": METRIC, "workload": "faults", "unit": "ms",
+            "config": {"workload": desc, "batch": "1e-3*|E| (80/20), 3 in sequence",
+                       "faults": "table entry per workgroup (w mod table length): "
+                                 "sleep after every claim, or stop at a claim boundary"},
+            "results": out}
+
+
 def batched(args, torch, dfpr, inputs):
     count = args.graphs or 1024
     t0 = time.time()
@@ -413,7 +444,8 @@ def main():
     assert torch.cuda.is_available(), "no HIP device"
     torch.cuda.set_device(0)
     fn = {"rmat22": headline, "rmat14": headline, "sweep": sweep,
-          "grid4096": grid, "batched1024": batched, "serving": serving}[args.workload]
+          "grid4096": grid, "batched1024": batched, "serving": serving,
+          "faults": faults}[args.workload]
     result = fn(args, torch, dfpr, inputs)
     print(json.dumps(result), flush=True)
 

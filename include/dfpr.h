@@ -50,7 +50,9 @@ extern "C" {
                                n <= 0, alpha outside (0,1), tol <= 0, ...  */
 #define DFPR_ENOMEM (-2)    /* device allocation failed; graph unchanged   */
 #define DFPR_EHIP (-3)      /* HIP runtime error; destroy the graph        */
-#define DFPR_EABORT (-4)    /* watchdog fired inside a kernel               */
+#define DFPR_EABORT (-4)    /* a kernel gave up (watchdog, or injected
+                               faults stopped every workgroup); marks are
+                               cleared and the ranks are unspecified       */
 #define DFPR_ESTATE (-5)    /* call not valid in the graph's current state */
 
 /* where an array argument lives */
@@ -183,6 +185,19 @@ int dfpr_naive_dynamic(dfpr_graph *g, dfpr_stats *stats);
  * watchdog fired. */
 int dfpr_static_lock_free(dfpr_graph *g, dfpr_stats *stats);
 int dfpr_naive_dynamic_lock_free(dfpr_graph *g, dfpr_stats *stats);
+
+/* Fault simulation (Sections 4.3 and 5.1, fault simulation): table[count]
+ * (host memory, copied) gives each workgroup w of the rank kernels the
+ * fault table[w % count], taken after every claim it completes: 0 none;
+ * d in (0, 1e6] sleep d microseconds (a random thread delay); -1 stop
+ * claiming (a crash-stop at a claim boundary: the workgroup holds no
+ * work when it stops, and the others finish its share).  A crash while
+ * holding a claim is not simulated; it would keep the lock-free scheme's
+ * in-flight count above zero until the watchdog (timeout_ms) aborts.
+ * count 0 clears the table.  Applies to dfpr_update, dfpr_static,
+ * dfpr_naive_dynamic and their lock-free forms, not to dfpr_update_many.
+ * DFPR_EINVAL for entries outside those values. */
+int dfpr_set_faults(dfpr_graph *g, const int32_t *table, int32_t count);
 
 /* Overwrites the ranks with r[n] (fp64; rounded for fp32 graphs). */
 int dfpr_set_ranks(dfpr_graph *g, const double *r, int mem);

@@ -82,7 +82,7 @@ static void release(dfpr_graph *g) {
                   g->sync_grab, g->sync_len, g->gflags, g->gwl,
                   g->ext2int, g->int2ext, g->steps,
                   g->split.lrow, g->split.lpre, g->split.lcnt, g->split.prow,
-                  g->split.ppart, g->split.xrow, g->tiles};
+                  g->split.ppart, g->split.xrow, g->tiles, g->faults};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (auto &s : g->scratch)
@@ -297,6 +297,25 @@ int dfpr_naive_dynamic_lock_free(dfpr_graph *g, dfpr_stats *stats) {
   if (!g) return fail(DFPR_EINVAL, "graph is NULL");
   if (stats) *stats = dfpr_stats{};
   return run_rank(g, 4, stats);
+}
+
+int dfpr_set_faults(dfpr_graph *g, const int32_t *table, int32_t count) {
+  if (!g) return fail(DFPR_EINVAL, "graph is NULL");
+  if (count < 0 || (count > 0 && !table)) return fail(DFPR_EINVAL, "bad fault table");
+  for (int32_t i = 0; i < count; ++i)
+    if (table[i] < -1 || table[i] > 1000000)
+      return fail(DFPR_EINVAL, "fault entries must be -1, 0 or a delay in (0, 1e6] us");
+  DFPR_HIP(hipStreamSynchronize(g->stream));
+  if (g->faults) {
+    DFPR_HIP(hipFree(g->faults));
+    g->faults = nullptr;
+  }
+  g->nfaults = 0;
+  if (count == 0) return DFPR_OK;
+  DFPR_HIP(hipMalloc(&g->faults, (size_t)count * 4));
+  DFPR_HIP(hipMemcpy(g->faults, table, (size_t)count * 4, hipMemcpyHostToDevice));
+  g->nfaults = count;
+  return DFPR_OK;
 }
 
 int dfpr_update(dfpr_graph *g, dfpr_stats *stats) {

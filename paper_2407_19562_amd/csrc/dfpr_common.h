@@ -65,7 +65,8 @@ enum SlotWord {
   kSlotEdges = 2,     // in-edges gathered (self-loops included)
   kSlotOut = 3,       // out-edges scanned by frontier expansion
   kSlotNewly = 4,     // vertices newly affected in this iteration
-  kSlotMaxDr = 5      // largest rank change of this iteration (fp64 bits)
+  kSlotMaxDr = 5,     // largest rank change of this iteration (fp64 bits)
+  kSlotItems = 6      // work items completed in this iteration
 };
 
 // Device control block of one graph.  The words every wavefront of the
@@ -168,6 +169,8 @@ struct dfpr_graph {
   hipGraphExec_t replay[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   uint64_t replay_key[2][2] = {{0, 0}, {0, 0}};
   hipStream_t capture_stream = nullptr;
+  int32_t *faults = nullptr;   // injected faults per workgroup (dfpr_set_faults)
+  int32_t nfaults = 0;
   dfpr::Split split;           // rows gathered in pieces
   int32_t *ext2int = nullptr;  // caller id -> internal id (null: identity)
   int32_t *int2ext = nullptr;  // internal id -> caller id

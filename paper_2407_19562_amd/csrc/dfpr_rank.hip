@@ -77,7 +77,27 @@ struct RankArgs {
   double *ppart;
   int32_t *lcnt;
   int32_t *xrow;                 // deferred long out-rows (Split)
+  const int32_t *faults;         // injected faults per workgroup (or null)
+  int32_t nfaults;
+  uint32_t ticks_per_us;         // wall-clock ticks per microsecond
 };
+
+// Injected fault of the calling workgroup, taken after each completed claim
+// (fault simulation: a delay, or a crash-stop at a claim boundary).
+// faults[blockIdx.x % nfaults]: 0 none, > 0 sleep that many microseconds,
+// < 0 stop claiming.  Returns true when the workgroup stops.
+template <typename T>
+__device__ __forceinline__ bool injected_fault(const RankArgs<T> &A) {
+  if (A.nfaults <= 0) return false;
+  const int32_t f = A.faults[blockIdx.x % (unsigned)A.nfaults];
+  if (f < 0) return true;
+  if (f > 0) {
+    const unsigned long long t0 = wall_clock64();
+    const unsigned long long d = (unsigned long long)f * A.ticks_per_us;
+    while (wall_clock64() - t0 < d) __builtin_amdgcn_s_sleep(64);
+  }
+  return false;
+}
 
 struct Counters {
   unsigned long long vertices = 0, edges = 0, out_scanned = 0;
@@ -600,6 +620,7 @@ __global__ void __launch_bounds__(256) k_df_async(RankArgs<T> A) {
     if (__builtin_amdgcn_readfirstlane(ab)) break;
     const int r = df_async_step<T>(A, L, cnt, newly, per, nullptr);
     if (r == kGraphDone) break;
+    if (r == kWorked && injected_fault(A)) break;  // holds no claim here
     if (r == kNoWork) {
       __builtin_amdgcn_s_sleep(32);
       if (A.timeout_ticks && ((polls & 63u) == 0) &&
@@ -674,6 +695,7 @@ __global__ void __launch_bounds__(256) k_sync_iter(RankArgs<T> A, const int32_t 
   Counters cnt;
   double maxdr = 0.0;
   long long newly = 0;  // vertices this wavefront marked for the first time
+  unsigned long long done_items = 0;
   // pieces of long rows first (their finishing wavefronts may still have
   // an out-row to mark), then the steps
   const unsigned long long packed = A.sync_len[iter];
@@ -692,6 +714,8 @@ __global__ void __launch_bounds__(256) k_sync_iter(RankArgs<T> A, const int32_t 
     if (u < npieces) {
       bool unused_moved = false;
       process_piece<T, MODE>(A, L, (int32_t)u, cnt, maxdr, newly, unused_moved);
+      ++done_items;
+      if (injected_fault(A)) break;
       continue;
     }
     u -= npieces;
@@ -704,6 +728,8 @@ __global__ void __launch_bounds__(256) k_sync_iter(RankArgs<T> A, const int32_t 
     }
     bool unused_moved = false;
     process_step<T, MODE>(A, L, vv, cnt, maxdr, newly, unused_moved);
+    ++done_items;
+    if (injected_fault(A)) break;
   }
   maxdr = wave_max(maxdr);
   const unsigned long long v = wave_sum(cnt.vertices);
@@ -718,6 +744,7 @@ __global__ void __launch_bounds__(256) k_sync_iter(RankArgs<T> A, const int32_t 
     if (e) atomicAdd(slot + kSlotEdges, e);
     if (o) atomicAdd(slot + kSlotOut, o);
     if (newly) atomicAdd(slot + kSlotNewly, (unsigned long long)newly);
+    if (done_items) atomicAdd(slot + kSlotItems, done_items);
   }
 }
 
@@ -774,20 +801,33 @@ __global__ void k_sync_finish(Ctl *ctl, unsigned long long *sync_max,
                               unsigned long long *slots,
                               double tol, int max_iters, int df) {
   const int t = threadIdx.x;
-  unsigned long long bits = 0;
+  unsigned long long bits = 0, items = 0;
   if (t < kClaimers) {
     unsigned long long *slot = slots + t * kClaimStride;
     bits = slot[kSlotMaxDr];
+    items = slot[kSlotItems];
     slot[kSlotClaim] = 0;
     slot[kSlotNewly] = 0;
     slot[kSlotMaxDr] = 0;
+    slot[kSlotItems] = 0;
   }
   // non-negative doubles order like their bit patterns
   bits = wave_max(bits);
+  items = wave_sum(items);
   if (t != 0) return;
   ctl->nexp = 0;
   if (ctl->sync_done) return;
   const int iter = ctl->iter;
+  const unsigned long long packed = sync_len[iter];
+  if (items != (packed >> 32) + (packed & 0xFFFFFFFFull)) {
+    // work items left unprocessed (every workgroup stopped by an injected
+    // fault): the iteration is incomplete
+    ctl->abort = 1;
+    ctl->sync_done = 1;
+    ctl->sync_final = iter + 1;
+    ctl->sync_conv = 0;
+    return;
+  }
   sync_max[iter] = bits;
   const double md = __longlong_as_double((long long)bits);
   if (md <= tol || iter + 1 >= max_iters) {
@@ -1107,6 +1147,9 @@ RankArgs<T> make_args(dfpr_graph *g, int rd, int wr) {
   A.ppart = g->split.ppart;
   A.lcnt = g->split.lcnt;
   A.xrow = g->split.xrow;
+  A.faults = g->faults;
+  A.nfaults = g->nfaults;
+  A.ticks_per_us = (uint32_t)(g->wallclock_khz / 1000 > 0 ? g->wallclock_khz / 1000 : 1);
   return A;
 }
 
@@ -1138,13 +1181,15 @@ double algorithmic_bytes(const dfpr_graph *g, const Ctl &h) {
 
 // Work items of one barrier-based iteration, built from the affected flags
 // (or from every vertex, for static PageRank) in three launches: per-tile
-// counts, a scan over tiles, and an emit pass.  A tile is kRows consecutive
-// vertex ids; its selected vertices keep id order.
+// counts, a scan over tiles, and an emit pass.  A tile is 256 or 1024
+// consecutive vertex ids (see tile_per); its selected vertices keep id
+// order.
 //   worklist  wl[0 .. tail) (affected vertices; not written for static)
 //   steps     worklist positions where a step starts, plus a sentinel: a
-//             step never crosses a tile, starts at the tile's first
-//             selected vertex and at every vertex whose in-edges reach past
-//             a multiple of kStepEdges of the tile's running count
+//             step never crosses a tile, starts at every kRows-th selected
+//             vertex of the tile (the first included) and at every vertex
+//             whose in-edges reach past a multiple of kStepEdges of the
+//             tile's running count
 //   pieces    rows with at least split_min in-edges count as one entry in
 //             the steps and are summed in pieces of kPiece in-edges:
 //             split.lrow (their ids), split.lpre (first piece of each),
@@ -1184,59 +1229,127 @@ __device__ __forceinline__ int32_t block_excl_scan(int32_t x, int32_t *lds4,
   return before + incl - x;
 }
 
+// Exclusive prefixes of K values over the 256-thread workgroup with one
+// pair of barriers; tot[f] = the workgroup's sum of value f.
+template <int K>
+__device__ __forceinline__ void block_excl_scan_k(const int32_t *x, int32_t *ex,
+                                                  int32_t *tot, int32_t (*lds)[256 / kWave]) {
+  const int lane = lane_id();
+  const int w = threadIdx.x / kWave;
+  int32_t incl[K];
+#pragma unroll
+  for (int f = 0; f < K; ++f) incl[f] = wave_incl_scan(x[f]);
+  __syncthreads();  // earlier readers of lds are done
+  if (lane == kWave - 1)
+#pragma unroll
+    for (int f = 0; f < K; ++f) lds[f][w] = incl[f];
+  __syncthreads();
+#pragma unroll
+  for (int f = 0; f < K; ++f) {
+    int32_t before = 0, sum = 0;
+#pragma unroll
+    for (int i = 0; i < 256 / kWave; ++i) {
+      const int32_t t = lds[f][i];
+      before += i < w ? t : 0;
+      sum += t;
+    }
+    ex[f] = before + incl[f] - x[f];
+    tot[f] = sum;
+  }
+}
+
+// A tile is 256 * PER consecutive ids, one 256-thread workgroup, PER ids
+// per thread: PER = 4 for large graphs (a quarter of the workgroups and
+// barriers: the 2^24-vertex grid's item building 8.3 -> 3.8 ms per update),
+// PER = 1 for small ones, where the latency of one pass matters more.
+constexpr int kTileLarge = 4;
+inline int tile_per(int32_t n) { return n >= (1 << 20) ? kTileLarge : 1; }
+
+template <int PER>
 struct TileScan {
-  int32_t v;       // vertex id (valid when sel)
-  bool sel, start, is_long;
-  int32_t rank;    // position among the tile's selected vertices
-  int32_t srank;   // position among the tile's step starts
-  int32_t lrank;   // position among the tile's long rows
-  int32_t ppre;    // first piece among the tile's pieces
-  int32_t npieces; // pieces of this row
+  int32_t v0;           // first id of the thread
+  bool sel[PER], start[PER], is_long[PER];
+  int32_t rank[PER];    // position among the tile's selected vertices
+  int32_t srank[PER];   // position among the tile's step starts
+  int32_t lrank[PER];   // position among the tile's long rows
+  int32_t ppre[PER];    // first piece among the tile's pieces
+  int32_t npieces[PER]; // pieces of the row
   TileSum tot;
 };
 
-// One tile per 256-thread block, one vertex per thread.
-template <bool ALL>
-__device__ __forceinline__ TileScan tile_scan(const uint8_t *flags,
-                                              const int32_t *deg, int32_t n,
-                                              int32_t split) {
-  __shared__ int32_t lds4[4];
-  TileScan r;
-  r.v = (int32_t)blockIdx.x * kRows + (int32_t)threadIdx.x;
-  r.sel = r.v < n && (ALL || flags[r.v] != 0);
-  const int32_t d = r.sel ? deg[r.v] : 0;
-  r.is_long = r.sel && d >= split;
-  const int32_t len = r.sel ? (r.is_long ? 1 : d + 1) : 0;
-  r.npieces = r.is_long ? (d + kPiece - 1) / kPiece : 0;
-  int32_t tsel, tlen, tlong, tpieces, tsteps;
-  r.rank = block_excl_scan(r.sel ? 1 : 0, lds4, &tsel);
-  const int32_t y = block_excl_scan(len, lds4, &tlen);
-  // a step starts at the first selected vertex and at every vertex whose
-  // in-edges reach past a multiple of kStepEdges of the running count
-  r.start = r.sel && (r.rank == 0 || (y + len - 1) / kStepEdges != (y - 1) / kStepEdges);
-  r.srank = block_excl_scan(r.start ? 1 : 0, lds4, &tsteps);
-  r.lrank = block_excl_scan(r.is_long ? 1 : 0, lds4, &tlong);
-  r.ppre = block_excl_scan(r.npieces, lds4, &tpieces);
-  r.tot = TileSum{tsel, tsteps, tlong, tpieces};
+template <bool ALL, int PER>
+__device__ __forceinline__ TileScan<PER> tile_scan(const uint32_t *flags,
+                                                   const int32_t *deg, int32_t n,
+                                                   int32_t split) {
+  constexpr int kPerThread = PER;
+  __shared__ int32_t lds[3][256 / kWave];
+  TileScan<PER> r;
+  r.v0 = (int32_t)blockIdx.x * 256 * PER + (int32_t)threadIdx.x * kPerThread;
+  const uint32_t fw = r.v0 < n ? flags[r.v0 >> 2] : 0u;
+  int32_t len[kPerThread];
+  int32_t c_sel = 0, c_len = 0;
+  int32_t loc_rank[kPerThread], loc_y[kPerThread];
+#pragma unroll
+  for (int q = 0; q < kPerThread; ++q) {
+    const int32_t v = r.v0 + q;
+    r.sel[q] = v < n && (ALL || ((fw >> (8 * (v & 3))) & 0xFFu) != 0);
+    const int32_t d = r.sel[q] ? deg[v] : 0;
+    r.is_long[q] = r.sel[q] && d >= split;
+    len[q] = r.sel[q] ? (r.is_long[q] ? 1 : d + 1) : 0;
+    r.npieces[q] = r.is_long[q] ? (d + kPiece - 1) / kPiece : 0;
+    loc_rank[q] = c_sel;
+    loc_y[q] = c_len;
+    c_sel += r.sel[q] ? 1 : 0;
+    c_len += len[q];
+  }
+  int32_t x2[2] = {c_sel, c_len}, b2[2], t2[2];
+  block_excl_scan_k<2>(x2, b2, t2, lds);
+  // a step starts every kRows selected vertices of the tile and at every
+  // vertex whose in-edges reach past a multiple of kStepEdges of the
+  // tile's running count
+  int32_t c_start = 0, c_long = 0, c_pieces = 0;
+  int32_t loc_s[kPerThread], loc_l[kPerThread], loc_p[kPerThread];
+#pragma unroll
+  for (int q = 0; q < kPerThread; ++q) {
+    r.rank[q] = b2[0] + loc_rank[q];
+    const int32_t y = b2[1] + loc_y[q];
+    r.start[q] = r.sel[q] && (r.rank[q] % kRows == 0 ||
+                              (y + len[q] - 1) / kStepEdges != (y - 1) / kStepEdges);
+    loc_s[q] = c_start;
+    loc_l[q] = c_long;
+    loc_p[q] = c_pieces;
+    c_start += r.start[q] ? 1 : 0;
+    c_long += r.is_long[q] ? 1 : 0;
+    c_pieces += r.npieces[q];
+  }
+  int32_t x3[3] = {c_start, c_long, c_pieces}, b3[3], t3[3];
+  block_excl_scan_k<3>(x3, b3, t3, lds);
+#pragma unroll
+  for (int q = 0; q < kPerThread; ++q) {
+    r.srank[q] = b3[0] + loc_s[q];
+    r.lrank[q] = b3[1] + loc_l[q];
+    r.ppre[q] = b3[2] + loc_p[q];
+  }
+  r.tot = TileSum{t2[0], t3[0], t3[1], t3[2]};
   return r;
 }
 
-template <bool ALL>
-__global__ void __launch_bounds__(256) k_tile_count(const uint8_t *flags,
+template <bool ALL, int PER>
+__global__ void __launch_bounds__(256) k_tile_count(const uint32_t *flags,
                                                     const int32_t *deg, int32_t n,
                                                     int32_t split, TileSum *sums,
                                                     const unsigned long long *slots,
                                                     int reuse) {
   if (reuse && slots_newly(slots) == 0) return;  // nothing newly affected: keep
-  const TileScan r = tile_scan<ALL>(flags, deg, n, split);
+  const TileScan<PER> r = tile_scan<ALL, PER>(flags, deg, n, split);
   if (threadIdx.x == 0) {
     sums[blockIdx.x] = r.tot;
     if (blockIdx.x == gridDim.x - 1) sums[gridDim.x] = TileSum{0, 0, 0, 0};
   }
 }
 
-template <bool ALL>
-__global__ void __launch_bounds__(256) k_tile_emit(const uint8_t *flags,
+template <bool ALL, int PER>
+__global__ void __launch_bounds__(256) k_tile_emit(const uint32_t *flags,
                                                    const int32_t *deg, int32_t n,
                                                    int32_t split, const TileSum *pre,
                                                    int32_t *wl, int32_t *steps,
@@ -1244,18 +1357,21 @@ __global__ void __launch_bounds__(256) k_tile_emit(const uint8_t *flags,
                                                    const unsigned long long *slots,
                                                    int reuse) {
   if (reuse && slots_newly(slots) == 0) return;
-  const TileScan r = tile_scan<ALL>(flags, deg, n, split);
+  const TileScan<PER> r = tile_scan<ALL, PER>(flags, deg, n, split);
   const TileSum b = pre[blockIdx.x];
-  if (r.sel) {
-    const int32_t pos = b.sel + r.rank;
-    if (!ALL) wl[pos] = r.v;
-    if (r.start) steps[b.steps + r.srank] = pos;
-    if (r.is_long) {
-      const int32_t j = b.nlong + r.lrank;
-      const int32_t p0 = b.pieces + r.ppre;
-      S.lrow[j] = r.v;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    if (!r.sel[q]) continue;
+    const int32_t v = r.v0 + q;
+    const int32_t pos = b.sel + r.rank[q];
+    if (!ALL) wl[pos] = v;
+    if (r.start[q]) steps[b.steps + r.srank[q]] = pos;
+    if (r.is_long[q]) {
+      const int32_t j = b.nlong + r.lrank[q];
+      const int32_t p0 = b.pieces + r.ppre[q];
+      S.lrow[j] = v;
       S.lpre[j] = p0;
-      for (int32_t k = 0; k < r.npieces; ++k) S.prow[p0 + k] = j;
+      for (int32_t k = 0; k < r.npieces[q]; ++k) S.prow[p0 + k] = j;
     }
   }
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
@@ -1354,6 +1470,7 @@ __global__ void __launch_bounds__(1024) k_tile_scan(const TileSum *sums, TileSum
   const int32_t b = (int32_t)threadIdx.x * per;
   const int32_t e = b + per < nt1 ? b + per : nt1;
   TileSum t{0, 0, 0, 0};
+#pragma unroll 8
   for (int32_t i = b; i < e; ++i) t = TileSumPlus()(t, sums[i]);
   int32_t v[4] = {t.sel, t.steps, t.nlong, t.pieces};
   int32_t ex[4];
@@ -1380,23 +1497,41 @@ __global__ void __launch_bounds__(1024) k_tile_scan(const TileSum *sums, TileSum
 // reuse: the previous items stay when the last iteration affected no new
 // vertex (decided on the device).
 void launch_items(dfpr_graph *g, bool all, bool reuse, hipStream_t s) {
-  const int32_t nt = (g->n + kRows - 1) / kRows;
+  const int per = tile_per(g->n);
+  const int32_t nt = (g->n + 256 * per - 1) / (256 * per);
   TileSum *sums = (TileSum *)g->tiles;
   TileSum *pre = sums + (nt + 1);
-  const uint8_t *fl = reinterpret_cast<const uint8_t *>(g->flags);
+  const uint32_t *fl = g->flags;
   const int32_t split = g->p.split_min_degree;
-  if (all)
-    k_tile_count<true><<<nt, 256, 0, s>>>(fl, g->in.deg, g->n, split, sums, g->sync_grab, 0);
-  else
-    k_tile_count<false><<<nt, 256, 0, s>>>(fl, g->in.deg, g->n, split, sums,
-                                           g->sync_grab, reuse);
-  k_tile_scan<<<1, 1024, 0, s>>>(sums, pre, nt + 1, g->sync_grab, all ? 0 : reuse);
-  if (all)
-    k_tile_emit<true><<<nt, 256, 0, s>>>(fl, g->in.deg, g->n, split, pre, g->wl, g->steps,
-                                         g->split, g->ctl, g->sync_grab, 0);
-  else
-    k_tile_emit<false><<<nt, 256, 0, s>>>(fl, g->in.deg, g->n, split, pre, g->wl, g->steps,
-                                          g->split, g->ctl, g->sync_grab, reuse);
+  const int ru = all ? 0 : (reuse ? 1 : 0);
+  const unsigned long long *sl = g->sync_grab;
+  if (per == kTileLarge) {
+    if (all)
+      k_tile_count<true, kTileLarge><<<nt, 256, 0, s>>>(fl, g->in.deg, g->n, split, sums, sl, 0);
+    else
+      k_tile_count<false, kTileLarge><<<nt, 256, 0, s>>>(fl, g->in.deg, g->n, split, sums, sl, ru);
+  } else {
+    if (all)
+      k_tile_count<true, 1><<<nt, 256, 0, s>>>(fl, g->in.deg, g->n, split, sums, sl, 0);
+    else
+      k_tile_count<false, 1><<<nt, 256, 0, s>>>(fl, g->in.deg, g->n, split, sums, sl, ru);
+  }
+  k_tile_scan<<<1, 1024, 0, s>>>(sums, pre, nt + 1, sl, ru);
+  if (per == kTileLarge) {
+    if (all)
+      k_tile_emit<true, kTileLarge><<<nt, 256, 0, s>>>(fl, g->in.deg, g->n, split, pre, g->wl,
+                                                       g->steps, g->split, g->ctl, sl, 0);
+    else
+      k_tile_emit<false, kTileLarge><<<nt, 256, 0, s>>>(fl, g->in.deg, g->n, split, pre, g->wl,
+                                                        g->steps, g->split, g->ctl, sl, ru);
+  } else {
+    if (all)
+      k_tile_emit<true, 1><<<nt, 256, 0, s>>>(fl, g->in.deg, g->n, split, pre, g->wl, g->steps,
+                                              g->split, g->ctl, sl, 0);
+    else
+      k_tile_emit<false, 1><<<nt, 256, 0, s>>>(fl, g->in.deg, g->n, split, pre, g->wl, g->steps,
+                                               g->split, g->ctl, sl, ru);
+  }
 }
 
 // Builds the work items of the next barrier-based iteration on the graph's
@@ -1495,8 +1630,8 @@ int run_sync(dfpr_graph *g, int mode, dfpr_stats *st) {
     // steps, pieces), and at most kSyncWavesPerCU per CU: measured on the
     // 2^22 R-MAT, 14 per CU beat both 8 and the 20 that fit
     const int wpb = g->p.block_size / kWave;
-    const int64_t nt = ((int64_t)g->n + kRows - 1) / kRows;
-    const int64_t items = nt + g->in.adj_cap / kStepEdges + 1 + g->split.pcap;
+    const int64_t items = 2 * (((int64_t)g->n + kRows - 1) / kRows) +
+                          g->in.adj_cap / kStepEdges + 1 + g->split.pcap;
     int64_t want = (items + wpb - 1) / wpb;
     const int64_t cap = (int64_t)kSyncWavesPerCU * (g->cu_count > 0 ? g->cu_count : 1) / wpb;
     if (want > cap) want = cap;
@@ -1594,6 +1729,8 @@ int run_sync(dfpr_graph *g, int mode, dfpr_stats *st) {
     }
     st->ms_kernel = ms;
   }
+  if (h.abort) return fail(DFPR_EABORT, "an iteration left work items unprocessed "
+                                       "(every workgroup stopped by an injected fault)");
   return h.sync_conv ? DFPR_OK : DFPR_NOTCONVERGED;
 }
 
@@ -1655,7 +1792,7 @@ int run_async(dfpr_graph *g, dfpr_stats *st, bool all = false) {
   g->last_launches = 1;
   if (st) {
     st->sweeps = sweeps;
-    st->converged = !capped && !h.abort;
+    st->converged = (h.state & kDone) && !capped && !h.abort;
     st->vertices_processed = (int64_t)h.vertices;
     st->edges_gathered = (int64_t)h.edges;
     st->out_edges_scanned = (int64_t)h.out_scanned;
@@ -1665,6 +1802,8 @@ int run_async(dfpr_graph *g, dfpr_stats *st, bool all = false) {
     st->ms_kernel = ms;
   }
   if (h.abort) return fail(DFPR_EABORT, "persistent kernel watchdog fired");
+  if (!(h.state & kDone))
+    return fail(DFPR_EABORT, "every workgroup stopped before the update converged");
   return capped ? DFPR_NOTCONVERGED : DFPR_OK;
 }
 

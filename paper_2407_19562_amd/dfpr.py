@@ -37,6 +37,7 @@ EXPORTS = (
     "dfpr_params_default", "dfpr_graph_create", "dfpr_graph_destroy",
     "dfpr_set_params", "dfpr_get_params", "dfpr_graph_size", "dfpr_static",
     "dfpr_naive_dynamic", "dfpr_static_lock_free", "dfpr_naive_dynamic_lock_free",
+    "dfpr_set_faults",
     "dfpr_set_ranks", "dfpr_read_ranks",
     "dfpr_apply_batch", "dfpr_update", "dfpr_update_many", "dfpr_read_edges",
     "dfpr_read_marks", "dfpr_graph_bytes", "dfpr_stream_copy",
@@ -105,6 +106,7 @@ def _lib():
             "dfpr_naive_dynamic": [V, P(dfpr_stats)],
             "dfpr_static_lock_free": [V, P(dfpr_stats)],
             "dfpr_naive_dynamic_lock_free": [V, P(dfpr_stats)],
+            "dfpr_set_faults": [V, P(ctypes.c_int32), ctypes.c_int32],
             "dfpr_set_ranks": [V, V, ctypes.c_int],
             "dfpr_read_ranks": [V, V, ctypes.c_int],
             "dfpr_apply_batch": [V, i64, V, V, i64, V, V, ctypes.c_int,
@@ -237,6 +239,14 @@ def dfpr_static_lock_free(g):
 def dfpr_naive_dynamic_lock_free(g):
     return _stats_call(_lib().dfpr_naive_dynamic_lock_free, g,
                        "dfpr_naive_dynamic_lock_free")
+
+
+def dfpr_set_faults(g, table) -> None:
+    """Per-workgroup fault table (see the header): 0 none, > 0 delay in
+    microseconds after each claim, -1 stop at a claim boundary."""
+    t = np.ascontiguousarray(np.asarray(table if table is not None else [], np.int32))
+    _check(_lib().dfpr_set_faults(g, t.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                  int(t.size)), "dfpr_set_faults")
 
 
 def dfpr_update(g):
@@ -393,6 +403,9 @@ class Graph:
 
     def naive_dynamic_lock_free(self):
         return dfpr_naive_dynamic_lock_free(self.h)
+
+    def set_faults(self, table):
+        dfpr_set_faults(self.h, table)
 
     def apply_batch(self, del_src, del_dst, ins_src, ins_dst):
         return dfpr_apply_batch(self.h, del_src, del_dst, ins_src, ins_dst)

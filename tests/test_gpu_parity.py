@@ -498,6 +498,52 @@ def test_lock_free_static_and_naive_dynamic(D, O, kind, prec):
         assert rel32(Rs, R0) < FP32_REL and rel32(Rn, R1) < FP32_REL
 
 
+@pytest.mark.parametrize("mode", ["sync", "async"])
+def test_injected_faults(D, O, mode):
+    # fault simulation: delayed workgroups and workgroups that stop at a
+    # claim boundary; the others finish the update, which still matches the
+    # oracle; with every workgroup stopped the call fails cleanly
+    say("faults", mode)
+    n, s, d = inputs.rmat_small()
+    R0, _, _ = O.pagerank(n, s, d)
+    b = inputs.batches(n, s, d, 1, 1001, frac=1e-3)[0]
+    ns, nd, res, _, _ = O.update(n, s, d, b, R0)
+    ref, _, _ = O.pagerank(n, ns, nd)
+    m = D.DFPR_SYNC if mode == "sync" else D.DFPR_ASYNC
+    with graph(D, n, s, d, mode=m) as g:
+        g.set_ranks(R0)
+        g.set_faults([0, -1, 0, 40, -1, 0, 0, -1])   # 3 of 8 stop, 1 delayed
+        g.apply(b)
+        rc, st = g.update()
+        assert rc == D.DFPR_OK and st.converged
+        assert err64(g.ranks(), ref) < FP64_TOL
+        if mode == "sync":
+            assert abs(st.sweeps - res.iters) <= 1
+        # every workgroup stops after one claim: the barrier-based launches
+        # still cover every item (a grid has at least as many wavefronts as
+        # an iteration of this graph has items, and each is relaunched per
+        # iteration); the persistent launch runs out of workers and fails
+        g.set_faults([-1])
+        ns2, nd2 = ns, nd
+        b2 = inputs.batches(n, ns, nd, 1, 1002, frac=1e-3)[0]
+        R1 = g.ranks()
+        g.apply(b2)
+        if mode == "sync":
+            ns2, nd2, res2, _, _ = O.update(n, ns, nd, b2, R1)
+            rc, st = g.update()
+            assert rc == D.DFPR_OK
+            ref2, _, _ = O.pagerank(n, ns2, nd2)
+            assert err64(g.ranks(), ref2) < FP64_TOL
+        else:
+            with pytest.raises(D.DfprError) as ei:
+                g.update()
+            assert ei.value.status == D.DFPR_EABORT
+        g.set_faults([])
+        with pytest.raises(D.DfprError) as ei:
+            g.set_faults([-2])
+        assert ei.value.status == D.DFPR_EINVAL
+
+
 def test_naive_dynamic_matches_oracle(D, O):
     say("naive dynamic")
     n, s, d = inputs.rmat_small()
