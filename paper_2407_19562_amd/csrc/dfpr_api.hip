@@ -311,10 +311,13 @@ int dfpr_set_faults(dfpr_graph *g, const int32_t *table, int32_t count) {
     g->faults = nullptr;
   }
   g->nfaults = 0;
+  g->fault_stops = 0;
   if (count == 0) return DFPR_OK;
   DFPR_HIP(hipMalloc(&g->faults, (size_t)count * 4));
   DFPR_HIP(hipMemcpy(g->faults, table, (size_t)count * 4, hipMemcpyHostToDevice));
   g->nfaults = count;
+  for (int32_t i = 0; i < count; ++i)
+    if (table[i] < 0) g->fault_stops = 1;
   return DFPR_OK;
 }
 

@@ -171,6 +171,7 @@ struct dfpr_graph {
   hipStream_t capture_stream = nullptr;
   int32_t *faults = nullptr;   // injected faults per workgroup (dfpr_set_faults)
   int32_t nfaults = 0;
+  int32_t fault_stops = 0;     // some entry stops its workgroups
   dfpr::Split split;           // rows gathered in pieces
   int32_t *ext2int = nullptr;  // caller id -> internal id (null: identity)
   int32_t *int2ext = nullptr;  // internal id -> caller id

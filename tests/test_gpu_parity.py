@@ -544,6 +544,30 @@ def test_injected_faults(D, O, mode):
         assert ei.value.status == D.DFPR_EINVAL
 
 
+def test_sync_claims_taken_over(D, O):
+    # a small grid (8 workgroups of 2 wavefronts) with every fourth
+    # workgroup stopping after one claim: the stopped wavefronts' claim
+    # counters hold several items each, which the others must take over;
+    # with every workgroup stopped the iteration is left incomplete and the
+    # call fails cleanly, after which the graph is usable again
+    say("sync claims taken over")
+    n, s, d = inputs.rmat_small()
+    ref, _, _ = O.pagerank(n, s, d)
+    with graph(D, n, s, d, mode=D.DFPR_SYNC) as g:
+        g.set_params(grid_blocks=8, block_size=128)
+        g.set_faults([-1, 0, 0, 0])
+        rc, st = g.static()
+        assert rc == D.DFPR_OK and st.converged
+        assert err64(g.ranks(), ref) < FP64_TOL
+        g.set_faults([-1])
+        with pytest.raises(D.DfprError) as ei:
+            g.static()
+        assert ei.value.status == D.DFPR_EABORT
+        g.set_faults([])
+        rc, st = g.static()
+        assert rc == D.DFPR_OK and err64(g.ranks(), ref) < FP64_TOL
+
+
 def test_naive_dynamic_matches_oracle(D, O):
     say("naive dynamic")
     n, s, d = inputs.rmat_small()
