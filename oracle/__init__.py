@@ -10,7 +10,8 @@ Layers:
   E^t = (E^{t-1} minus the deletions) union the insertions, vertex set fixed);
 * self-loops on every vertex (dead-end removal, Section 5.1.3);
 * fp64 iteration in plain C (``dfpr_oracle.c``): static PageRank of Eq. 1 /
-  Algorithm 3, and barrier-based Dynamic Frontier of Algorithm 1.
+  Algorithm 3, barrier-based Dynamic Frontier of Algorithm 1, and
+  barrier-based Dynamic Traversal of Algorithm 7.
 
 Readings taken where the paper is silent are listed in the design notes:
 self pairs in a batch are ignored (every vertex keeps its self-loop),
@@ -61,6 +62,8 @@ def _lib():
         lib.oracle_sweeps.argtypes = [i32, i64, p, p, dbl, i32, i32, p, p, p]
         lib.oracle_df_bb.argtypes = [i32, i64, p, p, i64, p, p, i64, p, p,
                                      dbl, dbl, dbl, i32, p, p, p, p, p, p, p]
+        lib.oracle_dt_bb.argtypes = [i32, i64, p, p, i64, p, p, i64, p, p,
+                                     dbl, dbl, i32, p, p, p, p, p, p, p]
         lib.oracle_residual.argtypes = [i32, i64, p, p, dbl, p, i32, p, p]
         lib.oracle_num_threads.restype = i32
         _lib_handle = lib
@@ -195,14 +198,7 @@ def df_bb(n: int, prev, cur, sources, R_prev, alpha: float = ALPHA,
     ``prev`` and ``cur`` are (src, dst) of G^{t-1} and G^t, ``sources`` the
     u of every true change (u, v) of the batch.  With ``self_loops`` both
     graphs get (v, v) on every vertex first."""
-    if self_loops:
-        ps, pt = with_self_loops(n, *prev)
-        cs, ct = with_self_loops(n, *cur)
-    else:
-        ps, pt = split_keys(n, edge_set(n, *prev))
-        cs, ct = split_keys(n, edge_set(n, *cur))
-    ps, pt, cs, ct = (np.ascontiguousarray(a, np.int32)
-                      for a in (ps, pt, cs, ct))
+    ps, pt, cs, ct = _prepared(n, prev, cur, self_loops)
     b = np.ascontiguousarray(sources, np.int32)
     Rp = np.ascontiguousarray(R_prev, np.float64)
     R = np.empty(n, np.float64)
@@ -221,6 +217,54 @@ def df_bb(n: int, prev, cur, sources, R_prev, alpha: float = ALPHA,
     return DFResult(R=R, affected=aff.astype(bool), iters=it.value,
                     last_dR=dR.value, initial_marked=im.value,
                     work_vertices=wv.value, work_edges=we.value)
+
+
+def _prepared(n, prev, cur, self_loops):
+    if self_loops:
+        ps, pt = with_self_loops(n, *prev)
+        cs, ct = with_self_loops(n, *cur)
+    else:
+        ps, pt = split_keys(n, edge_set(n, *prev))
+        cs, ct = split_keys(n, edge_set(n, *cur))
+    return tuple(np.ascontiguousarray(a, np.int32) for a in (ps, pt, cs, ct))
+
+
+def dt_bb(n: int, prev, cur, sources, R_prev, alpha: float = ALPHA,
+          tol: float = TOL, max_iters: int = MAX_ITERS,
+          self_loops: bool = True) -> DFResult:
+    """Dynamic Traversal, barrier-based (Algorithm 7) from R_prev: every
+    vertex reachable in G^t from the previous or current out-neighbours of
+    a batch source is affected, then Jacobi sweeps over that fixed set.
+    Arguments as for df_bb; ``initial_marked`` is the affected count."""
+    ps, pt, cs, ct = _prepared(n, prev, cur, self_loops)
+    b = np.ascontiguousarray(sources, np.int32)
+    Rp = np.ascontiguousarray(R_prev, np.float64)
+    R = np.empty(n, np.float64)
+    aff = np.empty(n, np.uint8)
+    it = ctypes.c_int32()
+    dR = ctypes.c_double()
+    im, wv, we = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    rc = _lib().oracle_dt_bb(n, ps.size, _ptr(ps), _ptr(pt), cs.size,
+                             _ptr(cs), _ptr(ct), b.size, _ptr(b), _ptr(Rp),
+                             alpha, tol, max_iters, _ptr(R), _ptr(aff),
+                             ctypes.byref(it), ctypes.byref(dR),
+                             ctypes.byref(im), ctypes.byref(wv),
+                             ctypes.byref(we))
+    if rc != 0:
+        raise ValueError(f"oracle_dt_bb failed ({rc})")
+    return DFResult(R=R, affected=aff.astype(bool), iters=it.value,
+                    last_dR=dR.value, initial_marked=im.value,
+                    work_vertices=wv.value, work_edges=we.value)
+
+
+def update_dt(n: int, src, dst, batch, R_prev, **kw):
+    """As update, with dt_bb in place of df_bb."""
+    s, t, d_true, i_true = apply_batch(n, src, dst, batch.del_src,
+                                       batch.del_dst, batch.ins_src,
+                                       batch.ins_dst)
+    sources = np.concatenate([d_true // n, i_true // n]).astype(np.int32)
+    res = dt_bb(n, (src, dst), (s, t), sources, R_prev, **kw)
+    return s, t, res, int(d_true.size), int(i_true.size)
 
 
 def update(n: int, src, dst, batch, R_prev, **kw):

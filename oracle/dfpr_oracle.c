@@ -21,6 +21,9 @@
  *     sweeps over the affected set; a vertex whose rank moves by more than
  *     the frontier tolerance marks its out-neighbours; stop when the
  *     L-infinity change of a sweep is <= tol.
+ *   - Algorithm 7 (Dynamic Traversal, barrier-based; Section 3.5.2): every
+ *     vertex reachable in the current graph from those out-neighbours is
+ *     affected, then the same sweeps without any further marking.
  *
  * Graphs arrive as CSR built here by a counting sort.  The caller (the
  * Python layer of the oracle) supplies edge sets that already carry the
@@ -28,7 +31,9 @@
  *
  * Parity pins for every function live in the CPU tests: closed forms,
  * the sum-to-one invariant, dense linear solves, brute force over all
- * 4-vertex digraphs, and the marking example of Section 4.1.2.
+ * 4-vertex digraphs, the marking example of Section 4.1.2 (and, derived
+ * by hand from Algorithm 7, its traversal marking), reachability from a
+ * library breadth-first search, and which ranks a change can move.
  */
 #include <math.h>
 #include <stdint.h>
@@ -288,6 +293,127 @@ int oracle_df_bb(int32_t n, int64_t mp, const int32_t *psrc,
 done:
   free(poff); free(pcol); free(coff); free(ccol); free(ioff); free(icol);
   free(VA); free(VAnext); free(R); free(Rn);
+  return rc;
+}
+
+/* Marks v and every vertex reachable from it in the CSR (off, col),
+ * depth first with an explicit stack.  A vertex is marked when it is
+ * pushed, so the stack never holds more than n entries; a vertex already
+ * marked was reached by an earlier search, which marked all it reaches. */
+static void visit_dfs(int32_t v, const int64_t *off, const int32_t *col,
+                      uint8_t *VA, int32_t *stack) {
+  if (VA[v]) return;
+  int64_t top = 0;
+  VA[v] = 1;
+  stack[top++] = v;
+  while (top > 0) {
+    int32_t x = stack[--top];
+    for (int64_t k = off[x]; k < off[x + 1]; ++k) {
+      int32_t y = col[k];
+      if (!VA[y]) {
+        VA[y] = 1;
+        stack[top++] = y;
+      }
+    }
+  }
+}
+
+/*
+ * Dynamic Traversal, barrier-based (Algorithm 7; Section 3.5.2).
+ *
+ * Inputs as for oracle_df_bb, without the frontier tolerance.
+ * Marking: for every batch source u and every v' in (G^{t-1} U G^t).out(u),
+ * v' and every vertex reachable from v' in G^t become affected.  Then
+ * Jacobi iterations of Eq. 1 on G^t over the affected set from Rprev: per
+ * iteration r for every affected v with the previous iteration's ranks,
+ * Rnew[v] = r; dR = max |Rnew - R|; swap; stop when dR <= tol or after
+ * max_iters iterations.  Nothing is marked during the iterations.
+ *
+ * Outputs: R_out[n]; affected_out[n] (may be null); *iters; *last_dR;
+ * *marked (the affected count); *work_vertices and *work_edges as for
+ * oracle_df_bb.
+ */
+int oracle_dt_bb(int32_t n, int64_t mp, const int32_t *psrc,
+                 const int32_t *pdst, int64_t mc, const int32_t *csrc,
+                 const int32_t *cdst, int64_t nb, const int32_t *bsrc,
+                 const double *Rprev, double alpha, double tol,
+                 int32_t max_iters, double *R_out, uint8_t *affected_out,
+                 int32_t *iters, double *last_dR, int64_t *marked,
+                 int64_t *work_vertices, int64_t *work_edges) {
+  if (check_edges(n, mp, psrc, pdst) || check_edges(n, mc, csrc, cdst) ||
+      !Rprev || !R_out || nb < 0)
+    return -1;
+  for (int64_t i = 0; i < nb; ++i)
+    if (bsrc[i] < 0 || bsrc[i] >= n) return -1;
+  int64_t *poff = malloc(sizeof(int64_t) * ((size_t)n + 1));
+  int32_t *pcol = malloc(sizeof(int32_t) * (size_t)(mp ? mp : 1));
+  int64_t *coff = malloc(sizeof(int64_t) * ((size_t)n + 1));
+  int32_t *ccol = malloc(sizeof(int32_t) * (size_t)(mc ? mc : 1));
+  int64_t *ioff = malloc(sizeof(int64_t) * ((size_t)n + 1));
+  int32_t *icol = malloc(sizeof(int32_t) * (size_t)(mc ? mc : 1));
+  uint8_t *VA = calloc((size_t)(n ? n : 1), 1);
+  int32_t *stack = malloc(sizeof(int32_t) * (size_t)(n ? n : 1));
+  double *R = malloc(sizeof(double) * (size_t)(n ? n : 1));
+  double *Rn = malloc(sizeof(double) * (size_t)(n ? n : 1));
+  int rc = 0;
+  if (!poff || !pcol || !coff || !ccol || !ioff || !icol || !VA || !stack ||
+      !R || !Rn) {
+    rc = -2;
+    goto done;
+  }
+  build_csr(n, mp, psrc, pdst, poff, pcol);   /* G^{t-1}.out */
+  build_csr(n, mc, csrc, cdst, coff, ccol);   /* G^t.out     */
+  build_csr(n, mc, cdst, csrc, ioff, icol);   /* G^t.in      */
+
+  /* Marking (Algorithm 7, before the first iteration): searches in G^t
+     from the previous and current out-neighbours of every batch source. */
+  for (int64_t i = 0; i < nb; ++i) {
+    int32_t u = bsrc[i];
+    for (int64_t k = poff[u]; k < poff[u + 1]; ++k)
+      visit_dfs(pcol[k], coff, ccol, VA, stack);
+    for (int64_t k = coff[u]; k < coff[u + 1]; ++k)
+      visit_dfs(ccol[k], coff, ccol, VA, stack);
+  }
+  int64_t cnt = 0;
+  for (int32_t v = 0; v < n; ++v) cnt += VA[v];
+  if (marked) *marked = cnt;
+
+  for (int32_t v = 0; v < n; ++v) R[v] = Rn[v] = Rprev[v];
+  const double base = (1.0 - alpha) / (double)n;
+  int32_t it = 0;
+  double dR = 0.0;
+  int64_t wv = 0, we = 0;
+  while (it < max_iters) {
+    for (int32_t v = 0; v < n; ++v) {
+      if (!VA[v]) continue;
+      double r = base;
+      for (int64_t k = ioff[v]; k < ioff[v + 1]; ++k) {
+        int32_t u = icol[k];
+        r += alpha * R[u] / (double)(coff[u + 1] - coff[u]);
+      }
+      Rn[v] = r;
+      wv += 1;
+      we += ioff[v + 1] - ioff[v];
+    }
+    ++it;
+    dR = 0.0;
+    for (int32_t v = 0; v < n; ++v) {
+      double d = fabs(Rn[v] - R[v]);
+      if (d > dR) dR = d;
+    }
+    /* unaffected vertices hold Rprev in both vectors */
+    double *t = R; R = Rn; Rn = t;
+    if (dR <= tol) break;
+  }
+  memcpy(R_out, R, sizeof(double) * (size_t)n);
+  if (affected_out) memcpy(affected_out, VA, (size_t)n);
+  if (iters) *iters = it;
+  if (last_dR) *last_dR = dR;
+  if (work_vertices) *work_vertices = wv;
+  if (work_edges) *work_edges = we;
+done:
+  free(poff); free(pcol); free(coff); free(ccol); free(ioff); free(icol);
+  free(VA); free(stack); free(R); free(Rn);
   return rc;
 }
 

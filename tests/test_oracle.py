@@ -7,6 +7,10 @@ paper, never by the oracle itself.
 * dense linear solves of (I - alpha M) R = (1 - alpha)/n for n <= 20;
 * brute force over all 4096 digraphs on 4 vertices;
 * Algorithm 1's marking on the worked example of Section 4.1.2;
+* Algorithm 7's traversal marking on the same example (derived by hand),
+  reachability from scipy's breadth-first search, and, over random small
+  digraphs and every single-edge change, that every vertex whose exact
+  rank moves is marked;
 * DF within the paper's error bound of the fixed point (Sections 4.4, 5.2);
 * stability round trip (Section 5.2.3); empty-batch identity;
 * set semantics of batch application (Section 3.4).
@@ -308,3 +312,119 @@ def test_df_stability_round_trip(oracle_lib):
     assert ni2 == nd1
     assert set(zip(s2.tolist(), d2.tolist())) == set(zip(s.tolist(), d.tolist()))
     assert np.abs(r2.R - R).max() < bound
+
+
+# --- Dynamic Traversal, Algorithm 7 ------------------------------------------
+
+def _example_batch(oracle_lib):
+    ex = _json("frontier_example.json")
+    n = ex["n"]
+    s, d = map(list, zip(*ex["edges_before"]))
+    (ds, dd), = ex["delete"]
+    (is_, id_), = ex["insert"]
+    ns, nd, dt, it = oracle_lib.apply_batch(n, s, d, [ds], [dd], [is_], [id_])
+    return n, (s, d), (ns, nd), np.concatenate([dt // n, it // n])
+
+
+@pytest.mark.parametrize("self_loops", [False, True])
+def test_traversal_example_marking(oracle_lib, self_loops):
+    tr = _json("traversal_example.json")
+    n, prev, cur, sources = _example_batch(oracle_lib)
+    r = oracle_lib.dt_bb(n, prev, cur, sources, np.full(n, 1.0 / n),
+                         max_iters=0, self_loops=self_loops)
+    key = "marked_with_self_loops" if self_loops else "marked_without_self_loops"
+    assert sorted(np.flatnonzero(r.affected).tolist()) == tr[key]
+    assert r.initial_marked == len(tr[key])
+
+
+def _reachable_bfs(n, src, dst, seeds):
+    """Vertices reachable from `seeds` (seeds included), by scipy's
+    breadth-first search from an extra vertex n with an edge to each seed."""
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import breadth_first_order
+    seeds = np.unique(np.asarray(seeds, np.int64))
+    rows = np.concatenate([np.asarray(src, np.int64), np.full(seeds.size, n)])
+    cols = np.concatenate([np.asarray(dst, np.int64), seeds])
+    A = csr_matrix((np.ones(rows.size), (rows, cols)), shape=(n + 1, n + 1))
+    order = breadth_first_order(A, n, directed=True, return_predecessors=False)
+    out = np.zeros(n, bool)
+    out[order[order < n]] = True
+    return out
+
+
+@pytest.mark.parametrize("frac", [1e-3, 1e-2])
+def test_traversal_marking_is_bfs_reachability(oracle_lib, frac):
+    n, s, d = inputs.rmat(10, 2 << 10, seed=6)      # sparse: not all reachable
+    R, _, _ = oracle_lib.pagerank(n, s, d)
+    b = inputs.batches(n, s, d, 1, 31, frac=frac)[0]
+    ns, nd, res, _, _ = oracle_lib.update_dt(n, s, d, b, R, max_iters=0)
+    ps, pt, dt, it = oracle_lib.apply_batch(n, s, d, b.del_src, b.del_dst,
+                                            b.ins_src, b.ins_dst)
+    sources = np.unique(np.concatenate([dt // n, it // n]))
+    # seeds: previous and current out-neighbours of each source, which
+    # with self-loops include the source itself
+    prev_out = np.isin(s, sources)
+    cur_out = np.isin(ns, sources)
+    seeds = np.concatenate([d[prev_out], nd[cur_out], sources])
+    want = _reachable_bfs(n, ns, nd, seeds)
+    assert 0 < want.sum() < n
+    assert np.array_equal(res.affected, want)
+
+
+def test_traversal_covers_every_moved_rank(oracle_lib):
+    # For random 5-vertex digraphs and every single-edge insertion or
+    # deletion: each vertex whose exact rank (dense solve) changes is
+    # marked, ranks of unmarked vertices are left bit-identical, and the
+    # result is within the tolerance's reach of the new fixed point.
+    rng = np.random.default_rng(12)
+    pairs = [(u, v) for u in range(5) for v in range(5) if u != v]
+    cases = 0
+    for _ in range(60):
+        mask = rng.random(len(pairs)) < 0.35
+        E = {pairs[i] for i in range(len(pairs)) if mask[i]}
+        s = [u for u, _ in E]
+        d = [v for _, v in E]
+        R0 = dense_pagerank(5, s, d)
+        for (u, v) in pairs:
+            E1 = E ^ {(u, v)}
+            s1 = [a for a, _ in E1]
+            d1 = [b for _, b in E1]
+            R1 = dense_pagerank(5, s1, d1)
+            r = oracle_lib.dt_bb(5, (s, d), (s1, d1), [u], R0)
+            moved = np.abs(R1 - R0) > 1e-14
+            assert not (moved & ~r.affected).any(), (sorted(E), (u, v))
+            assert np.array_equal(r.R[~r.affected], R0[~r.affected])
+            assert np.abs(r.R - R1).max() < 1e-9
+            cases += 1
+    assert cases == 60 * len(pairs)
+
+
+def test_traversal_contains_frontier(oracle_lib):
+    # DF only ever marks out-neighbours of affected vertices, so its final
+    # affected set lies inside the reachability closure of the same seeds
+    n, s, d = inputs.rmat(11, 8 << 11, seed=3)
+    R, _, _ = oracle_lib.pagerank(n, s, d)
+    b = inputs.batches(n, s, d, 1, 41, frac=1e-3)[0]
+    _, _, df, _, _ = oracle_lib.update(n, s, d, b, R)
+    _, _, dt, _, _ = oracle_lib.update_dt(n, s, d, b, R)
+    assert not (df.affected & ~dt.affected).any()
+    assert dt.initial_marked >= df.affected.sum()
+
+
+def test_traversal_within_paper_bound_rmat_small(oracle_lib):
+    bound = _json("paper_bounds.json")["df_linf_error_max"]
+    n, s, d = inputs.rmat_small()
+    R, _, _ = oracle_lib.pagerank(n, s, d)
+    b = inputs.batches(n, s, d, 1, 1001, frac=1e-3)[0]
+    ns, nd, res, _, _ = oracle_lib.update_dt(n, s, d, b, R)
+    ref, _, _ = oracle_lib.pagerank(n, ns, nd)
+    assert np.abs(res.R - ref).max() < bound
+    assert np.array_equal(res.R[~res.affected], R[~res.affected])
+
+
+def test_traversal_empty_batch_identity(oracle_lib):
+    n, s, d = inputs.rmat(10, 8 << 10, seed=4)
+    R, _, _ = oracle_lib.pagerank(n, s, d)
+    r = oracle_lib.dt_bb(n, (s, d), (s, d), np.empty(0, np.int32), R)
+    assert r.initial_marked == 0 and not r.affected.any()
+    assert np.array_equal(r.R, R)
