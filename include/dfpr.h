@@ -229,6 +229,28 @@ int dfpr_apply_batch(dfpr_graph *g, int64_t n_del, const int32_t *del_src,
  * `stats` may be NULL. */
 int dfpr_update(dfpr_graph *g, dfpr_stats *stats);
 
+/* Dynamic Traversal marking (Section 3.5.2; Algorithms 7 and 8, before the
+ * iterations): extends the marks of the batches applied since the last
+ * update to every vertex reachable from them along the current graph's
+ * out-edges, breadth first on the device.  Since dfpr_apply_batch marked
+ * (G^{t-1} U G^t).out(u) of every changed source u, the result is the
+ * affected set of Algorithm 7.  Every vertex it marks has had its out-row
+ * walked, so a following dfpr_update recomputes exactly this set and never
+ * grows it: the pair is the Dynamic Traversal update.  Marks added by a
+ * later dfpr_apply_batch before the update grow as Dynamic Frontier marks.
+ * *marked (may be NULL) receives the number of marked vertices.  Idempotent;
+ * with nothing marked it does nothing.  Errors: DFPR_EINVAL, DFPR_ENOMEM,
+ * DFPR_EHIP. */
+int dfpr_mark_reachable(dfpr_graph *g, int64_t *marked);
+
+/* Dynamic Traversal update (Algorithm 7 in DFPR_SYNC mode, Algorithm 8's
+ * lock-free scheme in DFPR_ASYNC mode): dfpr_mark_reachable followed by
+ * dfpr_update, timed together in stats->ms; stats->initial_marked is the
+ * size of the reachable set.  The lock-free scheme ends after a full sweep
+ * that moves no vertex by more than frontier_tol, as the lock-free static
+ * and naive-dynamic calls do.  Same returns as dfpr_update. */
+int dfpr_update_traversal(dfpr_graph *g, dfpr_stats *stats);
+
 /* Dynamic Frontier updates of `count` graphs in one persistent launch
  * (async scheduling only; all graphs on the same device, the first graph's
  * stream is used).  stats[count] may be NULL.  Returns the worst status. */

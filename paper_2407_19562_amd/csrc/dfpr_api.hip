@@ -327,6 +327,17 @@ int dfpr_update(dfpr_graph *g, dfpr_stats *stats) {
   return run_rank(g, 2, stats);
 }
 
+int dfpr_mark_reachable(dfpr_graph *g, int64_t *marked) {
+  if (!g) return fail(DFPR_EINVAL, "graph is NULL");
+  return mark_reachable(g, marked);
+}
+
+int dfpr_update_traversal(dfpr_graph *g, dfpr_stats *stats) {
+  if (!g) return fail(DFPR_EINVAL, "graph is NULL");
+  if (stats) *stats = dfpr_stats{};
+  return run_rank(g, 5, stats);
+}
+
 int dfpr_update_many(dfpr_graph *const *gs, int32_t count, dfpr_stats *stats) {
   if (count < 0 || (count > 0 && !gs)) return fail(DFPR_EINVAL, "bad graph list");
   for (int32_t i = 0; i < count; ++i)

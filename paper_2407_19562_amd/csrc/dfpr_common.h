@@ -137,6 +137,8 @@ struct Split {
 //                 out-rows to mark (after both directions are prepared)
 //   update        14 scan temporaries, 15 tile sums; update_many 12
 //                 descriptors; 13 rank staging of set/read calls
+//   traversal     8, 9 level lists, 10 level counters (marking, before an
+//                 update)
 struct Scratch {
   void *p = nullptr;
   size_t bytes = 0;
@@ -215,6 +217,10 @@ int check_params(const dfpr_params *p);
 // Builders (dfpr_build.hip).
 int build_graph(dfpr_graph *g, int64_t m, const int32_t *src,
                 const int32_t *dst);
+
+// Dynamic Traversal marking (dfpr_traverse.hip): extends the pending marks
+// to everything reachable from them; *marked (may be null) gets the total.
+int mark_reachable(dfpr_graph *g, int64_t *marked);
 
 // Ranks (dfpr_rank.hip).
 int init_uniform_ranks(dfpr_graph *g);
@@ -312,11 +318,6 @@ __device__ __forceinline__ int wave_append(bool want, int32_t v,
   return cnt;
 }
 
-// Marks v affected and lists its group.  vnew / gnew report whether v / its
-// group were new (decided by the atomics).  The pre-checks skip the atomics
-// when the bits are already set: coherent (agent-scope) ones inside the
-// lock-free kernel, plain ones elsewhere, where a stale read only costs an
-// extra atomic.
 // Marks v affected and lists its group with plain byte stores: valid while
 // no other bit of these bytes changes concurrently (the marking phase
 // between updates, where a byte only goes from 0 to the flag).
@@ -331,6 +332,11 @@ struct MarkOut {
   int32_t g;
 };
 
+// Marks v affected and lists its group.  vnew / gnew report whether v / its
+// group were new (decided by the atomics).  The pre-checks skip the atomics
+// when the bits are already set: coherent (agent-scope) ones inside the
+// lock-free kernel, plain ones elsewhere, where a stale read only costs an
+// extra atomic.
 __device__ __forceinline__ MarkOut mark_affected(uint32_t *flags,
                                                  uint32_t *gflags, int32_t v,
                                                  bool coherent = true) {

@@ -1935,6 +1935,12 @@ int run_rank(dfpr_graph *g, int kind, dfpr_stats *st) {
     int rc2 = finish_update(g);
     if (rc2) return rc2;
   } else {
+    if (kind == 5) {
+      // Dynamic Traversal: the closure of the marks, then the update over
+      // it (every marked vertex has its out-row walked, so nothing grows)
+      rc = mark_reachable(g, nullptr);
+      if (rc) return rc;
+    }
     if (g->pending_marks == 0) {
       // nothing affected: ranks stay bit-identical
       g->last_bytes = 0;

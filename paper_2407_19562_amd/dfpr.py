@@ -39,7 +39,8 @@ EXPORTS = (
     "dfpr_naive_dynamic", "dfpr_static_lock_free", "dfpr_naive_dynamic_lock_free",
     "dfpr_set_faults",
     "dfpr_set_ranks", "dfpr_read_ranks",
-    "dfpr_apply_batch", "dfpr_update", "dfpr_update_many", "dfpr_read_edges",
+    "dfpr_apply_batch", "dfpr_update", "dfpr_mark_reachable",
+    "dfpr_update_traversal", "dfpr_update_many", "dfpr_read_edges",
     "dfpr_read_marks", "dfpr_graph_bytes", "dfpr_stream_copy",
     "dfpr_last_kernel_bytes", "dfpr_strerror", "dfpr_last_error",
 )
@@ -112,6 +113,8 @@ def _lib():
             "dfpr_apply_batch": [V, i64, V, V, i64, V, V, ctypes.c_int,
                                  P(i64), P(i64)],
             "dfpr_update": [V, P(dfpr_stats)],
+            "dfpr_mark_reachable": [V, P(i64)],
+            "dfpr_update_traversal": [V, P(dfpr_stats)],
             "dfpr_update_many": [V, i32, V],
             "dfpr_read_edges": [V, ctypes.c_int, V, V, i64, P(i64)],
             "dfpr_read_marks": [V, V, P(i64)],
@@ -251,6 +254,16 @@ def dfpr_set_faults(g, table) -> None:
 
 def dfpr_update(g):
     return _stats_call(_lib().dfpr_update, g, "dfpr_update")
+
+
+def dfpr_mark_reachable(g) -> int:
+    c = ctypes.c_int64()
+    _check(_lib().dfpr_mark_reachable(g, ctypes.byref(c)), "dfpr_mark_reachable")
+    return int(c.value)
+
+
+def dfpr_update_traversal(g):
+    return _stats_call(_lib().dfpr_update_traversal, g, "dfpr_update_traversal")
 
 
 def dfpr_update_many(graphs):
@@ -416,6 +429,12 @@ class Graph:
 
     def update(self):
         return dfpr_update(self.h)
+
+    def mark_reachable(self) -> int:
+        return dfpr_mark_reachable(self.h)
+
+    def update_traversal(self):
+        return dfpr_update_traversal(self.h)
 
     def ranks(self, out=None):
         return dfpr_read_ranks(self.h, out)

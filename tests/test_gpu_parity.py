@@ -568,6 +568,95 @@ def test_sync_claims_taken_over(D, O):
         assert rc == D.DFPR_OK and err64(g.ranks(), ref) < FP64_TOL
 
 
+# --- Dynamic Traversal (Algorithms 7 and 8) ------------------------------------
+
+@pytest.mark.parametrize("case", ["sparse_rmat", "grid", "heavy_rows"])
+@pytest.mark.parametrize("reorder", [0, 1])
+def test_traversal_marks_match_oracle(D, O, case, reorder):
+    # the reachable set is unique: compared vertex by vertex; the grid needs
+    # ~100 levels (several host polls), the sparse R-MAT leaves part of the
+    # graph unreachable, heavy_rows walks out-rows of up to 20000 entries
+    say("traversal marks", case, reorder)
+    if case == "sparse_rmat":
+        n, s, d = inputs.rmat(12, 2 << 12, seed=6)
+    elif case == "grid":
+        n, s, d = inputs.grid_road(64, 3)
+    else:
+        n, s, d = inputs.heavy_rows()
+    R0, _, _ = O.pagerank(n, s, d)
+    b = inputs.batches(n, s, d, 1, 1003, frac=2e-4)[0]
+    ns, nd, res, ndel, nins = O.update_dt(n, s, d, b, R0, max_iters=0)
+    with graph(D, n, s, d, reorder=reorder) as g:
+        assert g.apply(b) == (ndel, nins)
+        cnt = g.mark_reachable()
+        aff, cnt2 = g.marks()
+        say("  marked", cnt, "oracle", res.initial_marked, "of", n)
+        assert cnt == cnt2 == res.initial_marked
+        assert np.array_equal(aff.astype(bool), res.affected)
+        assert g.mark_reachable() == cnt          # idempotent
+    if case == "sparse_rmat":
+        assert 0 < cnt < n
+
+
+@pytest.mark.parametrize("mode", ["sync", "async"])
+@pytest.mark.parametrize("prec", [64, 32])
+def test_traversal_update_matches_oracle(D, O, mode, prec):
+    say("traversal update", mode, prec)
+    n, s, d = inputs.rmat(12, 4 << 12, seed=9)
+    R0, _, _ = O.pagerank(n, s, d)
+    b = inputs.batches(n, s, d, 1, 1004, frac=1e-3)[0]
+    ns, nd, res, ndel, nins = O.update_dt(n, s, d, b, R0)
+    ref, _, _ = O.pagerank(n, ns, nd)
+    m = D.DFPR_SYNC if mode == "sync" else D.DFPR_ASYNC
+    with graph(D, n, s, d, mode=m, precision=prec,
+               renormalize=int(prec == 32)) as g:
+        g.set_ranks(R0)
+        R0d = g.ranks()                         # R0 as the graph stores it
+        assert g.apply(b) == (ndel, nins)
+        rc, st = g.update_traversal()
+        assert rc == D.DFPR_OK and st.converged, st.as_dict()
+        R = g.ranks()
+    say("  sweeps", st.sweeps, "oracle", res.iters, "marked", st.initial_marked,
+        res.initial_marked)
+    assert st.initial_marked == res.initial_marked
+    if prec == 64:
+        assert err64(R, ref) < FP64_TOL
+        assert err64(R, res.R) < FP64_TOL
+        # vertices outside the reachable set are never written
+        assert np.array_equal(R[~res.affected], R0d[~res.affected])
+    else:
+        assert rel32(R, ref) < FP32_REL
+    if mode == "sync":
+        assert st.affected == res.initial_marked
+        assert abs(st.sweeps - res.iters) <= 1
+
+
+def test_traversal_empty_and_repeat(D, O):
+    # nothing marked: no work, ranks bit-identical; a traversal update
+    # after a normal DF update starts from fresh marks
+    say("traversal empty")
+    n, s, d = inputs.rmat_small()
+    R0, _, _ = O.pagerank(n, s, d)
+    with graph(D, n, s, d) as g:
+        g.set_ranks(R0)
+        assert g.mark_reachable() == 0
+        rc, st = g.update_traversal()
+        assert rc == D.DFPR_OK and st.sweeps == 0
+        assert np.array_equal(g.ranks(), R0)
+        b1, b2 = inputs.batches(n, s, d, 2, 1005, frac=1e-3)
+        s1, d1, _, _, _ = O.update(n, s, d, b1, R0)
+        g.apply(b1)
+        rc, _ = g.update()
+        assert rc == D.DFPR_OK
+        R1 = g.ranks()
+        s2, d2, res2, _, _ = O.update_dt(n, s1, d1, b2, R1)
+        ref, _, _ = O.pagerank(n, s2, d2)
+        g.apply(b2)
+        rc, st = g.update_traversal()
+        assert rc == D.DFPR_OK and st.initial_marked == res2.initial_marked
+        assert err64(g.ranks(), ref) < FP64_TOL
+
+
 def test_naive_dynamic_matches_oracle(D, O):
     say("naive dynamic")
     n, s, d = inputs.rmat_small()
