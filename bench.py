@@ -12,7 +12,8 @@ on the same R-MAT, DF vs static recompute, fp64 and fp32), `grid4096`
 (4096x4096 road-like grid, lock-free vs synchronous, fp64 and fp32),
 `batched1024` (1024 small graphs in one launch vs one by one), `serving`
 (resident graphs under a Poisson stream of batches), `rmat14` (small R-MAT),
-`faults` (delayed or stopped workgroups, barrier-based vs lock-free).
+`faults` (delayed or stopped workgroups, barrier-based vs lock-free),
+`traversal` (Dynamic Traversal vs Dynamic Frontier vs naive-dynamic).
 """
 from __future__ import annotations
 
@@ -48,7 +49,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat22",
                     choices=["rmat22", "rmat14", "sweep", "grid4096",
-                             "batched1024", "serving", "faults"])
+                             "batched1024", "serving", "faults", "traversal"])
     ap.add_argument("--frac", type=float, default=1e-3)
     ap.add_argument("--precision", type=int, default=64, choices=[32, 64])
     ap.add_argument("--mode", default="sync", choices=["async", "sync"])
@@ -367,6 +368,55 @@ def faults(args, torch, dfpr, inputs):
             "results": out}
 
 
+def traversal(args, torch, dfpr, inputs):
+    """Dynamic Traversal against Dynamic Frontier and naive-dynamic
+    (barrier-based, fp64) on the 2^22 R-MAT and the road-like grid: per
+    batch size, 3 batches in sequence from the same static ranks, one graph
+    per method; time = apply + update wall time."""
+    out = {}
+    for name in ("rmat22", "grid4096"):
+        n, s, d, desc = load_workload(name)
+        ds, dd = torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda()
+        ov = overrides(args)
+        for f in (1e-7, 1e-5, 1e-3):
+            bs = inputs.batches(n, s, d, 3, seed=batch_seed(name, f) + 5, frac=f)
+            dev = device_batches(torch, bs)
+            for method in ("df", "dt", "nd"):
+                g = dfpr.Graph(n, ds, dd, mode=dfpr.DFPR_SYNC, **ov)
+                g.static()
+                lat, dev_ms, sweeps, aff = [], [], [], []
+                for b in dev:
+                    torch.cuda.synchronize()
+                    ts = time.perf_counter()
+                    g.apply_batch(*b)
+                    if method == "df":
+                        rc, st = g.update()
+                    elif method == "dt":
+                        rc, st = g.update_traversal()
+                    else:
+                        rc, st = g.naive_dynamic()
+                    lat.append((time.perf_counter() - ts) * 1e3)
+                    if rc < 0:
+                        raise RuntimeError(f"{method} failed {rc}")
+                    dev_ms.append(st.ms)
+                    sweeps.append(st.sweeps)
+                    aff.append(n if method == "nd" else st.affected)
+                g.close()
+                key = f"{name}_f{f:g}_{method}"
+                out[key] = {"ms_mean": statistics.mean(lat),
+                            "device_ms_mean": statistics.mean(dev_ms),
+                            "sweeps_mean": statistics.mean(sweeps),
+                            "affected_mean": statistics.mean(aff),
+                            "batch_edges": bs[0].size}
+                log(f"{key}: {out[key]}")
+    return {"metric": METRIC, "workload": "traversal", "unit": "ms",
+            "config": {"workload": "R-MAT 2^22 (seed 2) and 4096x4096 road-like grid (seed 3)",
+                       "batch": "f*|E| (80/20), 3 in sequence per size",
+                       "methods": "df: Dynamic Frontier (Algorithm 1); dt: Dynamic "
+                                  "Traversal (Algorithm 7); nd: naive-dynamic"},
+            "results": out}
+
+
 def batched(args, torch, dfpr, inputs):
     count = args.graphs or 1024
     t0 = time.time()
@@ -445,7 +495,7 @@ def main():
     torch.cuda.set_device(0)
     fn = {"rmat22": headline, "rmat14": headline, "sweep": sweep,
           "grid4096": grid, "batched1024": batched, "serving": serving,
-          "faults": faults}[args.workload]
+          "faults": faults, "traversal": traversal}[args.workload]
     result = fn(args, torch, dfpr, inputs)
     print(json.dumps(result), flush=True)
 

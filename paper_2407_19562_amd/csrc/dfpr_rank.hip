@@ -199,41 +199,56 @@ __device__ __forceinline__ int32_t flatten_rows(WaveLds<T> &L, const int64_t *of
 
 // Sums over the in-rows of the step's 256 vertices, edge-parallel: every
 // round loads kUnroll x 64 row entries, then as many contributions, all
-// independent, and adds them to the owners' LDS accumulators.
+// independent, and adds them to the owners' LDS accumulators.  The rounds
+// are software-pipelined: the owners and row entries of round k + 1 are
+// found and loaded while the contributions of round k are in flight, so a
+// round waits for one memory latency instead of two in a row.
 template <typename T, bool COH>
 __device__ __forceinline__ void gather_flat(const RankArgs<T> &A, WaveLds<T> &L,
                                             const int64_t *off,
                                             const int32_t *deg, double *sum) {
   const int lane = lane_id();
   const int32_t total = flatten_rows(L, off, deg);
-  for (int32_t base = 0; base < total; base += kUnroll * kWave) {
-    int own[kUnroll];
-    int32_t idx[kUnroll];
+  int own[kUnroll];
+  int32_t idx[kUnroll];
+  // Owners and row entries of the round starting at edge `base` (called
+  // with total > 0).  Lanes past the end load the last edge again and get
+  // owner -1: every load is unconditional, so no load sits in a branch that
+  // the compiler's wait-count tracking must treat as possibly skipped
+  // (which made it wait for all loads in flight before each contribution
+  // load).
+  auto fetch = [&](int32_t base) {
 #pragma unroll
     for (int j = 0; j < kUnroll; ++j) {
       const int32_t e = base + j * kWave + lane;
-      own[j] = -1;
-      idx[j] = 0;
-      if (e < total) {
-        own[j] = find_owner(L.pre, e);
-        idx[j] = A.in_adj[L.off[own[j]] + (e - L.pre[own[j]])];
-      }
+      const int32_t ec = e < total ? e : total - 1;
+      const int o = find_owner(L.pre, ec);
+      idx[j] = A.in_adj[L.off[o] + (ec - L.pre[o])];
+      own[j] = e < total ? o : -1;
     }
+  };
+  if (total > 0) fetch(0);
+  for (int32_t base = 0; base < total; base += kUnroll * kWave) {
+    int cur[kUnroll];
     T c[kUnroll];
 #pragma unroll
-    for (int j = 0; j < kUnroll; ++j)
-      c[j] = own[j] >= 0 ? ldc<T, COH>(A.Cr, idx[j]) : (T)0;
+    for (int j = 0; j < kUnroll; ++j) {
+      cur[j] = own[j];
+      c[j] = ldc<T, COH>(A.Cr, idx[j]);
+    }
+    const int32_t next = base + kUnroll * kWave;
+    if (next < total) fetch(next);
 #pragma unroll
     for (int j = 0; j < kUnroll; ++j) {
-      if (own[j] < 0) continue;
+      if (cur[j] < 0) continue;
       if constexpr (sizeof(T) == 8) {
-        atomicAdd(&L.acc[own[j]], (double)c[j]);
+        atomicAdd(&L.acc[cur[j]], (double)c[j]);
       } else {
-        const int32_t dlen = L.pre[own[j] + 1] - L.pre[own[j]];
+        const int32_t dlen = L.pre[cur[j] + 1] - L.pre[cur[j]];
         if (dlen >= A.kahan_min)
-          atomicAdd(&L.acc[own[j]], (double)c[j]);
+          atomicAdd(&L.acc[cur[j]], (double)c[j]);
         else
-          atomicAdd(&L.accf[own[j]], (float)c[j]);
+          atomicAdd(&L.accf[cur[j]], (float)c[j]);
       }
     }
   }
@@ -266,14 +281,15 @@ __device__ __forceinline__ void expand_flat(const RankArgs<T> &A, WaveLds<T> &L,
   const int32_t total = flatten_rows(L, oo, od);
   for (int32_t base = 0; base < total; base += kUnroll * kWave) {
     int32_t w[kUnroll];
+    // unconditional loads (lanes past the end repeat the last entry and
+    // are dropped), as in gather_flat
 #pragma unroll
     for (int j = 0; j < kUnroll; ++j) {
       const int32_t e = base + j * kWave + lane;
-      w[j] = -1;
-      if (e < total) {
-        const int o = find_owner(L.pre, e);
-        w[j] = A.out_adj[L.off[o] + (e - L.pre[o])];
-      }
+      const int32_t ec = e < total ? e : total - 1;
+      const int o = find_owner(L.pre, ec);
+      const int32_t x = A.out_adj[L.off[o] + (ec - L.pre[o])];
+      w[j] = e < total ? x : -1;
     }
 #pragma unroll
     for (int j = 0; j < kUnroll; ++j) {
@@ -412,18 +428,27 @@ __device__ void process_piece(const RankArgs<T> &A, WaveLds<T> &L, int32_t p,
   const int32_t a = (p - first) * kPiece;
   const int32_t b = a + kPiece < d ? a + kPiece : d;
   double part = 0.0;
-  for (int32_t e0 = a; e0 < b; e0 += kUnroll * kWave) {
-    int32_t idx[kUnroll];
+  // pipelined like gather_flat: the next round's row entries load while
+  // this round's contributions are in flight; lanes past the end load the
+  // last entry again and add nothing (a < b for every piece)
+  int32_t idx[kUnroll];
+  auto fetch = [&](int32_t e0) {
 #pragma unroll
     for (int q = 0; q < kUnroll; ++q) {
       const int32_t e = e0 + q * kWave + lane;
-      idx[q] = e < b ? row[e] : -1;
+      idx[q] = row[e < b ? e : b - 1];
     }
+  };
+  fetch(a);
+  for (int32_t e0 = a; e0 < b; e0 += kUnroll * kWave) {
     T c[kUnroll];
 #pragma unroll
-    for (int q = 0; q < kUnroll; ++q) c[q] = idx[q] >= 0 ? A.Cr[idx[q]] : (T)0;
+    for (int q = 0; q < kUnroll; ++q) c[q] = A.Cr[idx[q]];
+    const int32_t next = e0 + kUnroll * kWave;
+    if (next < b) fetch(next);
 #pragma unroll
-    for (int q = 0; q < kUnroll; ++q) part += (double)c[q];
+    for (int q = 0; q < kUnroll; ++q)
+      part += e0 + q * kWave + lane < b ? (double)c[q] : 0.0;
   }
   part = wave_sum(part);
   if (lane == 0) cnt.edges += (unsigned long long)(b - a);
