@@ -11,7 +11,9 @@ Layers:
 * self-loops on every vertex (dead-end removal, Section 5.1.3);
 * fp64 iteration in plain C (``dfpr_oracle.c``): static PageRank of Eq. 1 /
   Algorithm 3, barrier-based Dynamic Frontier of Algorithm 1, and
-  barrier-based Dynamic Traversal of Algorithm 7.
+  barrier-based Dynamic Traversal of Algorithm 7;
+* vertex insertion and removal with rescaled ranks before DF (the paper's
+  future-work remark), in numpy around the DF iteration.
 
 Readings taken where the paper is silent are listed in the design notes:
 self pairs in a batch are ignored (every vertex keeps its self-loop),
@@ -60,7 +62,7 @@ def _lib():
         lib.oracle_pagerank.argtypes = [i32, i64, p, p, dbl, dbl, i32, i32, p,
                                         p, p, p, p]
         lib.oracle_sweeps.argtypes = [i32, i64, p, p, dbl, i32, i32, p, p, p]
-        lib.oracle_df_bb.argtypes = [i32, i64, p, p, i64, p, p, i64, p, p,
+        lib.oracle_df_bb.argtypes = [i32, i64, p, p, i64, p, p, i64, p, p, p,
                                      dbl, dbl, dbl, i32, p, p, p, p, p, p, p]
         lib.oracle_dt_bb.argtypes = [i32, i64, p, p, i64, p, p, i64, p, p,
                                      dbl, dbl, i32, p, p, p, p, p, p, p]
@@ -192,12 +194,13 @@ class DFResult:
 
 def df_bb(n: int, prev, cur, sources, R_prev, alpha: float = ALPHA,
           tol: float = TOL, ftol: float = FTOL, max_iters: int = MAX_ITERS,
-          self_loops: bool = True) -> DFResult:
+          self_loops: bool = True, marks=None) -> DFResult:
     """Dynamic Frontier, barrier-based (Algorithm 1) from R_prev.
 
     ``prev`` and ``cur`` are (src, dst) of G^{t-1} and G^t, ``sources`` the
     u of every true change (u, v) of the batch.  With ``self_loops`` both
-    graphs get (v, v) on every vertex first."""
+    graphs get (v, v) on every vertex first.  ``marks`` (bool[n], optional)
+    adds initial marks made outside the two edge sets."""
     ps, pt, cs, ct = _prepared(n, prev, cur, self_loops)
     b = np.ascontiguousarray(sources, np.int32)
     Rp = np.ascontiguousarray(R_prev, np.float64)
@@ -206,8 +209,10 @@ def df_bb(n: int, prev, cur, sources, R_prev, alpha: float = ALPHA,
     it = ctypes.c_int32()
     dR = ctypes.c_double()
     im, wv, we = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    m0 = None if marks is None else np.ascontiguousarray(marks, np.uint8)
     rc = _lib().oracle_df_bb(n, ps.size, _ptr(ps), _ptr(pt), cs.size,
-                             _ptr(cs), _ptr(ct), b.size, _ptr(b), _ptr(Rp),
+                             _ptr(cs), _ptr(ct), b.size, _ptr(b), _ptr(m0),
+                             _ptr(Rp),
                              alpha, tol, ftol, max_iters, _ptr(R), _ptr(aff),
                              ctypes.byref(it), ctypes.byref(dR),
                              ctypes.byref(im), ctypes.byref(wv),
@@ -276,3 +281,64 @@ def update(n: int, src, dst, batch, R_prev, **kw):
     sources = np.concatenate([d_true // n, i_true // n]).astype(np.int32)
     res = df_bb(n, (src, dst), (s, t), sources, R_prev, **kw)
     return s, t, res, int(d_true.size), int(i_true.size)
+
+
+# --- vertex insertion and removal ---------------------------------------------
+#
+# The paper fixes the vertex set (Section 3.4) and names vertex additions
+# and deletions, with the existing ranks scaled before the computation, as
+# future work (Section 6).  Reading: Eq. 1's teleport term is (1-alpha)/n,
+# so multiplying a fixed point by n_old/n_new gives a fixed point for the
+# new term wherever the edges did not change; an added vertex starts at
+# 1/n_new, the rank of an isolated vertex with its self-loop.  Added
+# vertices take the next ids; removal takes the highest ids, with every
+# incident edge.
+
+def rescale(R_prev, n_new: int) -> np.ndarray:
+    """Ranks for a vertex count changed from R_prev.size to n_new: kept
+    vertices times n_old / n_new, added vertices at 1 / n_new."""
+    R_prev = np.asarray(R_prev, np.float64)
+    n_old = R_prev.size
+    f = float(n_old) / float(n_new)
+    keep = min(n_old, n_new)
+    R = np.full(n_new, 1.0 / n_new)
+    R[:keep] = R_prev[:keep] * f
+    return R
+
+
+def add_vertices_update(n: int, src, dst, k: int, batch, R_prev, **kw):
+    """k isolated vertices appended (ids n .. n+k-1), ranks rescaled, then
+    ``batch`` applied on the n+k vertices and DF run from the rescaled
+    ranks.  Returns (new_src, new_dst, DFResult, rescaled ranks)."""
+    n1 = n + k
+    R = rescale(R_prev, n1)
+    s, t, d_true, i_true = apply_batch(n1, src, dst, batch.del_src,
+                                       batch.del_dst, batch.ins_src,
+                                       batch.ins_dst)
+    sources = np.concatenate([d_true // n1, i_true // n1]).astype(np.int32)
+    res = df_bb(n1, (src, dst), (s, t), sources, R, **kw)
+    return s, t, res, R
+
+
+def remove_vertices_update(n: int, src, dst, k: int, R_prev, **kw):
+    """The k highest ids removed with every incident edge, ranks of the
+    others rescaled, then DF from the marks of those edge deletions: for
+    every source u of a removed edge, u itself (self-loop) and its previous
+    out-neighbours, among the remaining vertices.  Returns (new_src,
+    new_dst, DFResult, rescaled ranks)."""
+    n1 = n - k
+    src = np.asarray(src, np.int32)
+    dst = np.asarray(dst, np.int32)
+    e = edge_set(n, src, dst)
+    s0, t0 = split_keys(n, e)
+    keep = (s0 < n1) & (t0 < n1)
+    sources = np.unique(s0[~keep])
+    marks = np.zeros(n1, np.uint8)
+    out_prev = t0[np.isin(s0, sources)]
+    marks[out_prev[out_prev < n1]] = 1
+    marks[sources[sources < n1]] = 1
+    R = rescale(R_prev, n1)
+    s1, t1 = s0[keep], t0[keep]
+    res = df_bb(n1, (s1, t1), (s1, t1), np.empty(0, np.int32), R,
+                marks=marks, **kw)
+    return s1, t1, res, R

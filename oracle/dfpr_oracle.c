@@ -191,7 +191,8 @@ int oracle_sweeps(int32_t n, int64_t m, const int32_t *src,
  *
  * Inputs: the previous edge set (psrc, pdst; mp edges) and the current one
  * (csrc, cdst; mc edges), the batch sources bsrc[nb] (the u of every
- * (u, v) in the deletions and insertions), the previous ranks Rprev[n].
+ * (u, v) in the deletions and insertions), optional extra initial marks
+ * marks0[n] (may be null), the previous ranks Rprev[n].
  * Marking: every v' in (G^{t-1} U G^t).out(u) for every batch source u
  * becomes affected.  Then per iteration, for every vertex affected at the
  * start of that iteration: r from Eq. 1 on G^t with the previous
@@ -208,6 +209,7 @@ int oracle_sweeps(int32_t n, int64_t m, const int32_t *src,
 int oracle_df_bb(int32_t n, int64_t mp, const int32_t *psrc,
                  const int32_t *pdst, int64_t mc, const int32_t *csrc,
                  const int32_t *cdst, int64_t nb, const int32_t *bsrc,
+                 const uint8_t *marks0,
                  const double *Rprev, double alpha, double tol, double ftol,
                  int32_t max_iters, double *R_out, uint8_t *affected_out,
                  int32_t *iters, double *last_dR, int64_t *initial_marked,
@@ -237,7 +239,11 @@ int oracle_df_bb(int32_t n, int64_t mp, const int32_t *psrc,
   build_csr(n, mc, csrc, cdst, coff, ccol);   /* G^t.out     */
   build_csr(n, mc, cdst, csrc, ioff, icol);   /* G^t.in      */
 
-  /* Initial marking (Algorithm 1, before the first iteration). */
+  /* Initial marking (Algorithm 1, before the first iteration); marks0
+     adds marks made elsewhere (vertex removal: the out-neighbours of the
+     removed sources, which the vertex set here no longer holds). */
+  if (marks0)
+    for (int32_t v = 0; v < n; ++v) VA[v] = marks0[v] ? 1 : 0;
   for (int64_t i = 0; i < nb; ++i) {
     int32_t u = bsrc[i];
     for (int64_t k = poff[u]; k < poff[u + 1]; ++k) VA[pcol[k]] = 1;

@@ -13,7 +13,11 @@ paper, never by the oracle itself.
   rank moves is marked;
 * DF within the paper's error bound of the fixed point (Sections 4.4, 5.2);
 * stability round trip (Section 5.2.3); empty-batch identity;
-* set semantics of batch application (Section 3.4).
+* set semantics of batch application (Section 3.4);
+* vertex insertion and removal with rescaled ranks: adding isolated
+  vertices to a converged graph gives the new fixed point exactly (dense
+  solve), and DF after insertions or removals lands within the paper's
+  bound of the static fixed point of the new graph.
 """
 import itertools
 import json
@@ -428,3 +432,60 @@ def test_traversal_empty_batch_identity(oracle_lib):
     r = oracle_lib.dt_bb(n, (s, d), (s, d), np.empty(0, np.int32), R)
     assert r.initial_marked == 0 and not r.affected.any()
     assert np.array_equal(r.R, R)
+
+
+# --- vertex insertion and removal (rescaled ranks) --------------------------------
+
+def test_add_isolated_vertices_rescaling_is_exact(oracle_lib):
+    rng = np.random.default_rng(21)
+    n, k = 12, 3
+    E = {(int(u), int(v)) for u, v in rng.integers(0, n, (40, 2)) if u != v}
+    s = [u for u, _ in E]
+    d = [v for _, v in E]
+    R0 = dense_pagerank(n, s, d)
+    empty = inputs.Batch(*(np.empty(0, np.int32) for _ in range(4)))
+    ns, nd, res, R = oracle_lib.add_vertices_update(n, s, d, k, empty, R0)
+    want = dense_pagerank(n + k, s, d)
+    assert np.abs(R - want).max() < TIGHT          # rescaling alone
+    assert res.initial_marked == 0
+    assert np.abs(res.R - want).max() < TIGHT
+
+
+def test_add_vertices_then_edges_within_bound(oracle_lib):
+    bound = _json("paper_bounds.json")["df_linf_error_max"]
+    n, s, d = inputs.rmat(10, 8 << 10, seed=12)
+    k = 64
+    R0, _, _ = oracle_lib.pagerank(n, s, d)
+    rng = np.random.default_rng(4)
+    new = np.arange(n, n + k, dtype=np.int32)
+    old = rng.integers(0, n, k).astype(np.int32)
+    # each new vertex gets an edge to and from an old vertex
+    b = inputs.Batch(np.empty(0, np.int32), np.empty(0, np.int32),
+                     np.concatenate([new, old]), np.concatenate([old, new]))
+    ns, nd, res, R = oracle_lib.add_vertices_update(n, s, d, k, b, R0)
+    ref, _, _ = oracle_lib.pagerank(n + k, ns, nd)
+    assert np.abs(res.R - ref).max() < bound
+    assert abs(res.R.sum() - 1) < 1e-9
+
+
+@pytest.mark.parametrize("k", [1, 50])
+def test_remove_vertices_within_bound(oracle_lib, k):
+    bound = _json("paper_bounds.json")["df_linf_error_max"]
+    n, s, d = inputs.erdos_renyi(1000, 6000, 8)
+    R0, _, _ = oracle_lib.pagerank(n, s, d)
+    ns, nd, res, R = oracle_lib.remove_vertices_update(n, s, d, k, R0)
+    assert max(ns.max(), nd.max()) < n - k
+    assert ns.size < s.size                      # incident edges went too
+    ref, _, _ = oracle_lib.pagerank(n - k, ns, nd)
+    assert np.abs(res.R - ref).max() < bound
+    assert abs(res.R.sum() - 1) < 1e-9
+
+
+def test_add_then_remove_round_trip(oracle_lib):
+    n, s, d = inputs.rmat(9, 8 << 9, seed=2)
+    R0, _, _ = oracle_lib.pagerank(n, s, d)
+    empty = inputs.Batch(*(np.empty(0, np.int32) for _ in range(4)))
+    s1, d1, r1, _ = oracle_lib.add_vertices_update(n, s, d, 7, empty, R0)
+    s2, d2, r2, _ = oracle_lib.remove_vertices_update(n + 7, s1, d1, 7, r1.R)
+    assert r2.initial_marked == 0
+    assert np.abs(r2.R - R0).max() < 1e-15
