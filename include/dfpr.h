@@ -229,6 +229,35 @@ int dfpr_apply_batch(dfpr_graph *g, int64_t n_del, const int32_t *del_src,
  * `stats` may be NULL. */
 int dfpr_update(dfpr_graph *g, dfpr_stats *stats);
 
+/* Vertex insertion (an extension: the paper keeps the vertex set fixed,
+ * Section 3.4, and names vertex additions with ranks scaled before the
+ * computation as future work, Section 6).  Appends `count` vertices with
+ * caller ids n .. n+count-1 (*first_id, may be NULL, receives n) and no
+ * edges but their self-loops.  Every existing rank is multiplied by
+ * n / (n+count) and the new ranks are 1 / (n+count): with Eq. 1's teleport
+ * term (1-alpha)/n this maps a fixed point of the old graph to one of the
+ * new graph exactly, so nothing is marked.  Edges to and from the new
+ * vertices are ordinary batches (dfpr_apply_batch, then dfpr_update).
+ * Pending marks are kept.  Per-vertex device arrays are reallocated (the
+ * call synchronizes the graph's stream); on DFPR_ENOMEM the graph is
+ * unchanged.  Errors: DFPR_EINVAL (count <= 0, or n + count above
+ * 2^31 - 2), DFPR_ENOMEM, DFPR_EHIP. */
+int dfpr_add_vertices(dfpr_graph *g, int32_t count, int32_t *first_id);
+
+/* Vertex removal (the same extension): removes the `count` highest caller
+ * ids n-count .. n-1 with every edge incident to them.  Those edges are
+ * deleted as one batch (marking the remaining out-neighbours of their
+ * sources, and the sources, as dfpr_apply_batch does), the removed ids'
+ * marks are dropped, and every remaining rank is multiplied by
+ * n / (n-count); the next dfpr_update recomputes the marked vertices.
+ * To remove other vertices, give them the highest ids first.  A graph
+ * whose internal order was changed at creation (reorder) accepts removal
+ * only of vertices it keeps in the caller's order there (those added by
+ * dfpr_add_vertices).  Synchronizes the graph's stream.  Errors:
+ * DFPR_EINVAL (count outside [1, n), or reordered ids), DFPR_ENOMEM,
+ * DFPR_EHIP. */
+int dfpr_remove_vertices(dfpr_graph *g, int32_t count);
+
 /* Dynamic Traversal marking (Section 3.5.2; Algorithms 7 and 8, before the
  * iterations): extends the marks of the batches applied since the last
  * update to every vertex reachable from them along the current graph's

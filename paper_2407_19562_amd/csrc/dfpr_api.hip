@@ -327,6 +327,16 @@ int dfpr_update(dfpr_graph *g, dfpr_stats *stats) {
   return run_rank(g, 2, stats);
 }
 
+int dfpr_add_vertices(dfpr_graph *g, int32_t count, int32_t *first_id) {
+  if (!g) return fail(DFPR_EINVAL, "graph is NULL");
+  return add_vertices(g, count, first_id);
+}
+
+int dfpr_remove_vertices(dfpr_graph *g, int32_t count) {
+  if (!g) return fail(DFPR_EINVAL, "graph is NULL");
+  return remove_vertices(g, count);
+}
+
 int dfpr_mark_reachable(dfpr_graph *g, int64_t *marked) {
   if (!g) return fail(DFPR_EINVAL, "graph is NULL");
   return mark_reachable(g, marked);

@@ -222,6 +222,10 @@ int build_graph(dfpr_graph *g, int64_t m, const int32_t *src,
 // to everything reachable from them; *marked (may be null) gets the total.
 int mark_reachable(dfpr_graph *g, int64_t *marked);
 
+// Vertex insertion and removal with rescaled ranks (dfpr_vertices.hip).
+int add_vertices(dfpr_graph *g, int32_t count, int32_t *first_id);
+int remove_vertices(dfpr_graph *g, int32_t count);
+
 // Ranks (dfpr_rank.hip).
 int init_uniform_ranks(dfpr_graph *g);
 int refresh_contributions(dfpr_graph *g);

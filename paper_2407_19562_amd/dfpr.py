@@ -39,7 +39,8 @@ EXPORTS = (
     "dfpr_naive_dynamic", "dfpr_static_lock_free", "dfpr_naive_dynamic_lock_free",
     "dfpr_set_faults",
     "dfpr_set_ranks", "dfpr_read_ranks",
-    "dfpr_apply_batch", "dfpr_update", "dfpr_mark_reachable",
+    "dfpr_apply_batch", "dfpr_update", "dfpr_add_vertices",
+    "dfpr_remove_vertices", "dfpr_mark_reachable",
     "dfpr_update_traversal", "dfpr_update_many", "dfpr_read_edges",
     "dfpr_read_marks", "dfpr_graph_bytes", "dfpr_stream_copy",
     "dfpr_last_kernel_bytes", "dfpr_strerror", "dfpr_last_error",
@@ -114,6 +115,8 @@ def _lib():
                                  P(i64), P(i64)],
             "dfpr_update": [V, P(dfpr_stats)],
             "dfpr_mark_reachable": [V, P(i64)],
+            "dfpr_add_vertices": [V, i32, P(i32)],
+            "dfpr_remove_vertices": [V, i32],
             "dfpr_update_traversal": [V, P(dfpr_stats)],
             "dfpr_update_many": [V, i32, V],
             "dfpr_read_edges": [V, ctypes.c_int, V, V, i64, P(i64)],
@@ -254,6 +257,17 @@ def dfpr_set_faults(g, table) -> None:
 
 def dfpr_update(g):
     return _stats_call(_lib().dfpr_update, g, "dfpr_update")
+
+
+def dfpr_add_vertices(g, count: int) -> int:
+    first = ctypes.c_int32()
+    _check(_lib().dfpr_add_vertices(g, int(count), ctypes.byref(first)),
+           "dfpr_add_vertices")
+    return int(first.value)
+
+
+def dfpr_remove_vertices(g, count: int) -> None:
+    _check(_lib().dfpr_remove_vertices(g, int(count)), "dfpr_remove_vertices")
 
 
 def dfpr_mark_reachable(g) -> int:
@@ -429,6 +443,17 @@ class Graph:
 
     def update(self):
         return dfpr_update(self.h)
+
+    def add_vertices(self, count: int) -> int:
+        """Appends `count` isolated vertices; returns the first new id."""
+        first = dfpr_add_vertices(self.h, count)
+        self.n, _ = dfpr_graph_size(self.h)
+        return first
+
+    def remove_vertices(self, count: int) -> None:
+        """Removes the `count` highest ids with their edges."""
+        dfpr_remove_vertices(self.h, count)
+        self.n, _ = dfpr_graph_size(self.h)
 
     def mark_reachable(self) -> int:
         return dfpr_mark_reachable(self.h)

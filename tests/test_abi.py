@@ -87,6 +87,19 @@ def test_strerror_and_bad_params(lib):
                                ctypes.byref(out)) == lib.DFPR_EINVAL
 
 
+def test_null_graph_is_rejected(lib):
+    # every graph entry point checks its handle before any device call
+    h = lib._lib()
+    for name, args in [("dfpr_add_vertices", (1, None)),
+                       ("dfpr_remove_vertices", (1,)),
+                       ("dfpr_mark_reachable", (None,)),
+                       ("dfpr_update_traversal", (None,)),
+                       ("dfpr_update", (None,)),
+                       ("dfpr_set_faults", (None, 0))]:
+        assert getattr(h, name)(None, *args) == lib.DFPR_EINVAL, name
+        assert "NULL" in lib.dfpr_last_error()
+
+
 @pytest.mark.parametrize("field,value", [
     ("chunk", 32), ("chunk", 100), ("chunk", 8192), ("block_size", 96),
     ("block_size", 512), ("reorder", 3), ("split_min_degree", 0),

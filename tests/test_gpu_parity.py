@@ -657,6 +657,92 @@ def test_traversal_empty_and_repeat(D, O):
         assert err64(g.ranks(), ref) < FP64_TOL
 
 
+# --- vertex insertion and removal (rescaled ranks) -------------------------------
+
+@pytest.mark.parametrize("reorder", [0, 1])
+@pytest.mark.parametrize("mode", ["sync", "async"])
+def test_add_vertices_matches_oracle(D, O, mode, reorder):
+    say("add vertices", mode, reorder)
+    n, s, d = inputs.rmat_small()
+    k = 100
+    R0, _, _ = O.pagerank(n, s, d)
+    rng = np.random.default_rng(17)
+    new = np.arange(n, n + k, dtype=np.int32)
+    old = rng.integers(0, n, k).astype(np.int32)
+    b = inputs.Batch(np.empty(0, np.int32), np.empty(0, np.int32),
+                     np.concatenate([new, old, new[:10]]),
+                     np.concatenate([old, new, new[10:20]]))
+    ns, nd, res, Rs = O.add_vertices_update(n, s, d, k, b, R0)
+    ref, _, _ = O.pagerank(n + k, ns, nd)
+    m = D.DFPR_SYNC if mode == "sync" else D.DFPR_ASYNC
+    with graph(D, n, s, d, mode=m, reorder=reorder) as g:
+        g.set_ranks(R0)
+        assert g.add_vertices(k) == n
+        assert g.size() == (n + k, s.size)
+        assert np.array_equal(g.ranks(), Rs)          # same fp64 product
+        assert g.marks()[1] == 0
+        g.apply(b)
+        rc, st = g.update()
+        assert rc == D.DFPR_OK and st.converged, st.as_dict()
+        assert st.initial_marked == res.initial_marked
+        R = g.ranks()
+        es, ed = g.edges(D.DFPR_OUT)
+    assert np.array_equal(edge_keys(n + k, es, ed), edge_keys(n + k, ns, nd))
+    assert err64(R, ref) < FP64_TOL
+
+
+@pytest.mark.parametrize("mode", ["sync", "async"])
+def test_remove_vertices_matches_oracle(D, O, mode):
+    say("remove vertices", mode)
+    n, s, d = inputs.erdos_renyi(3000, 20000, 5)
+    k = 120
+    R0, _, _ = O.pagerank(n, s, d)
+    _, _, res0, Rs = O.remove_vertices_update(n, s, d, k, R0, max_iters=0)
+    ns, nd, res, _ = O.remove_vertices_update(n, s, d, k, R0)
+    ref, _, _ = O.pagerank(n - k, ns, nd)
+    m = D.DFPR_SYNC if mode == "sync" else D.DFPR_ASYNC
+    with graph(D, n, s, d, mode=m) as g:
+        g.set_ranks(R0)
+        g.remove_vertices(k)
+        assert g.size() == (n - k, ns.size)
+        assert np.array_equal(g.ranks(), Rs)
+        aff, cnt = g.marks()
+        assert cnt == res0.initial_marked
+        assert np.array_equal(aff, res0.affected)
+        rc, st = g.update()
+        assert rc == D.DFPR_OK and st.converged, st.as_dict()
+        R = g.ranks()
+        es, ed = g.edges(D.DFPR_OUT)
+    assert np.array_equal(edge_keys(n - k, es, ed), edge_keys(n - k, ns, nd))
+    assert err64(R, ref) < FP64_TOL
+
+
+def test_vertices_round_trip_and_errors(D, O):
+    say("vertices round trip")
+    n, s, d = inputs.rmat_small()
+    # hubs at the highest ids: a degree-sorted graph moves them inside
+    s, d = (n - 1 - s).astype(np.int32), (n - 1 - d).astype(np.int32)
+    R0, _, _ = O.pagerank(n, s, d)
+    with graph(D, n, s, d, reorder=1) as g:
+        g.set_ranks(R0)
+        with pytest.raises(D.DfprError) as ei:
+            g.remove_vertices(3)
+        assert ei.value.status == D.DFPR_EINVAL
+        for bad in (0, n):
+            with pytest.raises(D.DfprError):
+                g.remove_vertices(bad)
+        with pytest.raises(D.DfprError):
+            g.add_vertices(0)
+        assert g.add_vertices(7) == n
+        g.remove_vertices(7)                  # added vertices keep their ids
+        assert g.size() == (n, s.size)
+        assert float(np.abs(g.ranks() - R0).max()) < 1e-15
+        rc, st = g.update()                   # nothing was marked
+        assert rc == D.DFPR_OK and st.sweeps == 0
+        es, ed = g.edges(D.DFPR_OUT)
+        assert np.array_equal(edge_keys(n, es, ed), edge_keys(n, s, d))
+
+
 def test_naive_dynamic_matches_oracle(D, O):
     say("naive dynamic")
     n, s, d = inputs.rmat_small()
