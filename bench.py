@@ -13,7 +13,8 @@ on the same R-MAT, DF vs static recompute, fp64 and fp32), `grid4096`
 `batched1024` (1024 small graphs in one launch vs one by one), `serving`
 (resident graphs under a Poisson stream of batches), `rmat14` (small R-MAT),
 `faults` (delayed or stopped workgroups, barrier-based vs lock-free),
-`traversal` (Dynamic Traversal vs Dynamic Frontier vs naive-dynamic).
+`traversal` (Dynamic Traversal vs Dynamic Frontier vs naive-dynamic),
+`vertices` (vertex insertion and removal with rescaled ranks).
 """
 from __future__ import annotations
 
@@ -49,7 +50,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat22",
                     choices=["rmat22", "rmat14", "sweep", "grid4096",
-                             "batched1024", "serving", "faults", "traversal"])
+                             "batched1024", "serving", "faults", "traversal", "vertices"])
     ap.add_argument("--frac", type=float, default=1e-3)
     ap.add_argument("--precision", type=int, default=64, choices=[32, 64])
     ap.add_argument("--mode", default="sync", choices=["async", "sync"])
@@ -417,6 +418,55 @@ def traversal(args, torch, dfpr, inputs):
             "results": out}
 
 
+def vertices(args, torch, dfpr, inputs):
+    """Vertex insertion and removal on the 2^22 R-MAT (fp64, barrier-based
+    DF): add k vertices with 16 in- and 16 out-edges each to random old
+    vertices, or remove the k highest ids with their edges, then update;
+    against a static recompute of the resulting graph.  k = 1e-5 n, 1e-4 n
+    and 1e-3 n; times are wall times of each call."""
+    n, s, d, desc = load_workload("rmat22")
+    ds, dd = torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda()
+    ov = overrides(args)
+    out = {}
+    rng = np.random.default_rng(4242)
+    for frac in (1e-5, 1e-4, 1e-3):
+        k = max(1, int(round(frac * n)))
+        for op in ("add", "remove"):
+            g = dfpr.Graph(n, ds, dd, mode=dfpr.DFPR_SYNC, reorder=0, **ov)
+            g.static()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if op == "add":
+                first = g.add_vertices(k)
+                t1 = time.perf_counter()
+                new = np.repeat(np.arange(first, first + k, dtype=np.int32), 16)
+                old = rng.integers(0, n, new.size).astype(np.int32)
+                b = inputs.Batch(np.empty(0, np.int32), np.empty(0, np.int32),
+                                 np.concatenate([new, old]), np.concatenate([old, new]))
+                g.apply(b)
+            else:
+                g.remove_vertices(k)
+                t1 = time.perf_counter()
+            t2 = time.perf_counter()
+            rc, st = g.update()
+            t3 = time.perf_counter()
+            if rc < 0:
+                raise RuntimeError(f"update failed {rc}")
+            rc2, st2 = g.static()
+            g.close()
+            key = f"{op}_k{k}"
+            out[key] = {"vertex_call_ms": (t1 - t0) * 1e3, "apply_ms": (t2 - t1) * 1e3,
+                        "update_ms": (t3 - t2) * 1e3, "total_ms": (t3 - t0) * 1e3,
+                        "sweeps": st.sweeps, "affected": st.affected,
+                        "static_ms": st2.ms, "static_iters": st2.sweeps}
+            log(f"{key}: {out[key]}")
+    return {"metric": METRIC, "workload": "vertices", "unit": "ms",
+            "config": {"workload": desc + ", caller order (reorder 0)",
+                       "change": "add k vertices with 16 in- and 16 out-edges each, "
+                                 "or remove the k highest ids with their edges"},
+            "results": out}
+
+
 def batched(args, torch, dfpr, inputs):
     count = args.graphs or 1024
     t0 = time.time()
@@ -495,7 +545,8 @@ def main():
     torch.cuda.set_device(0)
     fn = {"rmat22": headline, "rmat14": headline, "sweep": sweep,
           "grid4096": grid, "batched1024": batched, "serving": serving,
-          "faults": faults, "traversal": traversal}[args.workload]
+          "faults": faults, "traversal": traversal,
+          "vertices": vertices}[args.workload]
     result = fn(args, torch, dfpr, inputs)
     print(json.dumps(result), flush=True)
 

@@ -58,6 +58,21 @@ __global__ void k_count_flags(const uint32_t *flags, int64_t words, Ctl *ctl) {
   if (lane_id() == 0 && c) atomicAdd((unsigned long long *)&ctl->marked, c);
 }
 
+// Copies rows first .. first+count-1 of one adjacency direction to
+// out[pos[i] ..] (one wavefront per row).
+__global__ void k_gather_rows(const int64_t *off, const int32_t *deg, const int32_t *adj,
+                              int32_t first, int32_t count, const int64_t *pos,
+                              int32_t *out) {
+  const int lane = lane_id();
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+  const int64_t waves = (int64_t)gridDim.x * blockDim.x / kWave;
+  for (int64_t i = wave; i < count; i += waves) {
+    const int64_t o = off[first + i];
+    const int32_t d = deg[first + i];
+    for (int32_t j = lane; j < d; j += kWave) out[pos[i] + j] = adj[o + j];
+  }
+}
+
 // Reallocates *p from old_bytes to new_bytes, keeping the contents; the new
 // tail is set to `fill` (a byte value) unless fill < 0.
 int grow(dfpr_graph *g, void **p, size_t old_bytes, size_t new_bytes, int fill) {
@@ -166,22 +181,36 @@ int remove_vertices(dfpr_graph *g, int32_t count) {
     i2e.resize((size_t)n0);
     DFPR_HIP(hipMemcpy(i2e.data(), g->int2ext, (size_t)n0 * 4, hipMemcpyDeviceToHost));
   }
-  // every edge incident to a removed vertex, in caller ids
+  // every edge incident to a removed vertex, in caller ids: the removed
+  // rows of both directions are gathered on the device and copied once
   std::vector<int32_t> ds, dd;
   for (int dir = 0; dir < 2; ++dir) {
     const Adj &A = dir == 0 ? g->out : g->in;
-    std::vector<int64_t> off((size_t)count);
     std::vector<int32_t> deg((size_t)count);
-    DFPR_HIP(hipMemcpy(off.data(), A.off + n1, (size_t)count * 8, hipMemcpyDeviceToHost));
     DFPR_HIP(hipMemcpy(deg.data(), A.deg + n1, (size_t)count * 4, hipMemcpyDeviceToHost));
+    std::vector<int64_t> pos((size_t)count);
+    int64_t total = 0;
     for (int32_t i = 0; i < count; ++i) {
-      const int32_t d = deg[(size_t)i];
-      if (d <= 0) continue;
-      std::vector<int32_t> row((size_t)d);
-      DFPR_HIP(hipMemcpy(row.data(), A.adj + off[(size_t)i], (size_t)d * 4,
-                         hipMemcpyDeviceToHost));
+      pos[(size_t)i] = total;
+      total += deg[(size_t)i];
+    }
+    if (total == 0) continue;
+    void *dpos = nullptr, *drows = nullptr;
+    int rc;
+    if ((rc = scratch_get(g, 8, (size_t)count * 8, &dpos))) return rc;
+    if ((rc = scratch_get(g, 9, (size_t)total * 4, &drows))) return rc;
+    DFPR_HIP(hipMemcpyAsync(dpos, pos.data(), (size_t)count * 8, hipMemcpyHostToDevice, s));
+    k_gather_rows<<<vgrid((int64_t)count * kWave, g->cu_count), kVBlock, 0, s>>>(
+        A.off, A.deg, A.adj, n1, count, static_cast<const int64_t *>(dpos),
+        static_cast<int32_t *>(drows));
+    DFPR_HIP(hipGetLastError());
+    std::vector<int32_t> rows((size_t)total);
+    DFPR_HIP(hipMemcpyAsync(rows.data(), drows, (size_t)total * 4, hipMemcpyDeviceToHost, s));
+    DFPR_HIP(hipStreamSynchronize(s));
+    for (int32_t i = 0; i < count; ++i) {
       const int32_t r = n1 + i;
-      for (int32_t x : row) {
+      for (int64_t j = pos[(size_t)i]; j < pos[(size_t)i] + deg[(size_t)i]; ++j) {
+        const int32_t x = rows[(size_t)j];
         const int32_t xe = i2e.empty() ? x : i2e[(size_t)x];
         ds.push_back(dir == 0 ? r : xe);
         dd.push_back(dir == 0 ? xe : r);
