@@ -109,7 +109,7 @@ typedef struct {
                             each update                                     */
   int32_t timeout_ms;    /* watchdog for the persistent kernel (0: none)    */
   int32_t grid_blocks;   /* workgroups of the rank kernels; 0 = automatic:
-                            barrier-based, at most 14 wavefronts per CU and
+                            barrier-based, at most 12 wavefronts per CU and
                             no more than an iteration's work items;
                             lock-free, about four claims per wavefront per
                             sweep                                           */

@@ -116,8 +116,10 @@ __device__ __forceinline__ T ldc(const T *C, int32_t u) {
 // (row r = k * 64 + lane holds the lane's k-th vertex).
 constexpr int kQ = 4;
 constexpr int kRows = kQ * kWave;
-// independent row entries (and then contributions) each lane loads per round
-constexpr int kUnroll = 8;
+// independent row entries (and then contributions) each lane loads per
+// round; with the rounds pipelined, 6 measured best on the 2^22 R-MAT (4, 5
+// and 8 were 1-3% slower)
+constexpr int kUnroll = 6;
 
 // Per-wavefront LDS: the flattened edge list of the current step (prefix of
 // the row lengths and the row starts) and per-row accumulators.
@@ -1243,7 +1245,7 @@ double algorithmic_bytes(const dfpr_graph *g, const Ctl &h) {
 // Totals land in ctl->tail / nsteps / nlong / npieces.  Rows of fewer
 // in-edges are never split, so a step can exceed kStepEdges by one row.
 constexpr int32_t kStepEdges = 16384;
-constexpr int kSyncWavesPerCU = 14;
+constexpr int kSyncWavesPerCU = 12;
 
 struct TileSum {
   int32_t sel, steps, nlong, pieces;
@@ -1674,7 +1676,7 @@ int run_sync(dfpr_graph *g, int mode, dfpr_stats *st) {
   if (g->p.grid_blocks <= 0) {
     // no more wavefronts than an iteration can have items (tiles, edge
     // steps, pieces), and at most kSyncWavesPerCU per CU: measured on the
-    // 2^22 R-MAT, 14 per CU beat both 8 and the 20 that fit
+    // 2^22 R-MAT with the pipelined gather, 12 per CU beat 8, 10, 14 and 16
     const int wpb = g->p.block_size / kWave;
     const int64_t items = 2 * (((int64_t)g->n + kRows - 1) / kRows) +
                           g->in.adj_cap / kStepEdges + 1 + g->split.pcap;
