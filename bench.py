@@ -507,15 +507,18 @@ def batched(args, torch, dfpr, inputs):
         t_batched = (time.perf_counter() - t) * 1e3
         t = time.perf_counter()
         for g in sets[1]:
-            g.update()
+            rc1, g.last_stats = g.update()
         t_seq = (time.perf_counter() - t) * 1e3
         edges = sum(st.edges_gathered for st in stats)
-        diff = max(float(np.abs(a.ranks() - b.ranks()).max()) for a, b in zip(*sets))
+        diffs = [float(np.abs(a.ranks() - b.ranks()).max()) for a, b in zip(*sets)]
         out[f"fp{prec}"] = {"batched_ms": t_batched, "sequential_ms": t_seq,
                             "speedup": t_seq / t_batched,
                             "edges_gathered": edges,
+                            "edges_gathered_sequential": sum(g.last_stats.edges_gathered
+                                                             for g in sets[1]),
                             "edges_per_s_batched": edges / (t_batched * 1e-3),
-                            "max_abs_diff_batched_vs_alone": diff}
+                            "max_abs_diff_batched_vs_alone": max(diffs),
+                            "graphs_differing": sum(x > 0 for x in diffs)}
         log(f"fp{prec}: {out[f'fp{prec}']}")
         for hs in sets:
             for g in hs:
