@@ -419,18 +419,20 @@ __global__ void k_mark_sources(int64_t S, const int64_t *segstart,
   }
 }
 
-// Out-rows deferred by k_mark_sources: every wavefront of the launch takes
-// its share of 64-entry chunks of every such row.
+// Out-rows deferred by k_mark_sources: one workgroup per row (rows strided
+// over the workgroups), its threads striding over the row.  Having every
+// thread of the grid walk every row in turn left most threads idle and made
+// the launch a chain of per-row load latencies (1.1 ms per 1e-3 batch on
+// the 2^22 R-MAT).
 __global__ void k_mark_long(const int32_t *long_list, AdjView out, uint32_t *flags,
                             uint32_t *gflags, const Ctl *ctl) {
-  const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int64_t nt = (int64_t)gridDim.x * blockDim.x;
   const unsigned long long cnt = ctl->nlong_mark;
-  for (unsigned long long j = 0; j < cnt; ++j) {
+  for (unsigned long long j = blockIdx.x; j < cnt; j += gridDim.x) {
     const int32_t u = long_list[j];
     const int64_t off = out.off[u];
     const int32_t deg = out.deg[u];
-    for (int64_t idx = t0; idx < deg; idx += nt) mark_plain(flags, gflags, out.adj[off + idx]);
+    for (int32_t idx = threadIdx.x; idx < deg; idx += blockDim.x)
+      mark_plain(flags, gflags, out.adj[off + idx]);
   }
 }
 
