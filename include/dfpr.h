@@ -118,7 +118,12 @@ typedef struct {
                             captured once in a HIP graph and replayed (kernel
                             time is then reported for the whole loop);
                             2 (default) replay when the graph has at most
-                            2^22 in-edge slots, where launches dominate    */
+                            2^22 in-edge slots, where launches dominate.
+                            A capture that fails (other threads' device
+                            calls can invalidate it) falls back to
+                            launching the iterations one by one; callers
+                            that drive graphs from several threads at once
+                            are better off with 0                          */
 } dfpr_params;
 
 typedef struct {

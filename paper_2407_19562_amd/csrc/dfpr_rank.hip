@@ -1706,10 +1706,14 @@ int run_sync(dfpr_graph *g, int mode, dfpr_stats *st) {
   const bool replay = g->p.graph_replay == 1 ||
                       (g->p.graph_replay == 2 && g->in.adj_cap <= (int64_t(1) << 22));
   hipGraphExec_t exec = nullptr;
-  if (replay) {
-    int rc = replay_graph<T>(g, mode, blocks, lds, launch_iteration, &exec);
-    if (rc) return rc;
-  } else {
+  if (replay && replay_graph<T>(g, mode, blocks, lds, launch_iteration, &exec) != DFPR_OK) {
+    // a capture can fail when other threads drive the device meanwhile;
+    // replay only saves launch overhead, so the iterations run launched
+    // one by one instead (nothing captured has run)
+    (void)hipGetLastError();
+    exec = nullptr;
+  }
+  if (!exec) {
     while ((int)g->iter_ev.size() < 2 * iters) {
       hipEvent_t e = nullptr;
       DFPR_HIP(hipEventCreate(&e));

@@ -2,16 +2,24 @@
 applied with continuous batching.
 
 Every graph keeps its slack CSR and ranks resident on the device.  Requests
-(one update batch for one graph) queue per graph in arrival order.  The
-loop runs in rounds: each round admits the requests that have arrived (as
-long as free device memory covers their staging), picks the graphs with
-queued requests (at most `max_graphs`, longest-waiting first), applies
-their queued batches in FIFO order (at most `coalesce` per graph; batches
-applied before one update accumulate their marks, which is the same as
-applying their union), and then updates those graphs, together in one
-persistent launch (dfpr_update_many) or one by one.  A request completes when the round
-that applied it finishes; its latency runs from arrival to that moment.
-Requests arriving during a round join the next one.
+(one update batch for one graph) queue per graph in arrival order.  Requests are
+admitted as they arrive (as long as free device memory covers their
+staging).  A graph's queued batches are applied in FIFO order (at most
+`coalesce` at a time; batches applied before one update accumulate their
+marks, which is the same as applying their union) and then the graph is
+updated.  Two schemes:
+  each     (default) every graph is served independently: whenever a graph
+           with queued requests is idle and fewer than `max_graphs` graphs
+           are in flight, a worker thread applies and updates it on the
+           graph's own stream (barrier-based scheme), so the graphs' work
+           overlaps on the device; its requests complete when that update
+           does.  No graph waits for another graph's update.
+  batched  rounds: the graphs with queued requests (at most `max_graphs`,
+           longest-waiting first) are applied and then updated together in
+           one persistent lock-free launch (dfpr_update_many); requests
+           complete when their round does, and those arriving during a
+           round join the next one.
+A request's latency runs from its arrival to its completion.
 """
 from __future__ import annotations
 
@@ -45,7 +53,8 @@ class Report:
     admission_waits: int = 0
     apply_s: float = 0.0      # time spent applying batches (batched scheme)
     update_s: float = 0.0     # time spent in rank updates (each scheme:
-                              # applies and updates, overlapped)
+                              # the whole run, applies and updates
+                              # overlapped)
 
     def summary(self):
         lat = np.array(self.latencies_ms) if self.latencies_ms else np.zeros(1)
@@ -65,13 +74,12 @@ class Report:
 class Server:
     """Resident graphs plus the continuous-batching loop.
 
-    scheme "batched": each round updates its graphs together in one
-    persistent lock-free launch (dfpr_update_many).  scheme "each"
-    (default): each graph has its own stream, and a round applies and
-    updates each of its graphs (barrier-based scheme) from a worker thread,
-    so the graphs' work overlaps on the device.  A round takes at most `max_graphs`
-    graphs (0: all with queued requests), those whose oldest request has
-    waited longest, so a round stays short under load."""
+    scheme "each" (default): graphs are served independently, at most
+    `max_graphs` at a time (0: no limit), each from a worker thread on its
+    own stream.  scheme "batched": rounds of at most `max_graphs` graphs
+    updated together in one persistent lock-free launch
+    (dfpr_update_many).  In both, the graphs whose oldest request has waited
+    longest go first."""
 
     def __init__(self, graphs, precision: int = 32, coalesce: int = 16,
                  reserve_bytes: int = 1 << 30, scheme: str = "each",
@@ -89,15 +97,22 @@ class Server:
             # device (the library's calls release the interpreter lock)
             import concurrent.futures
             import torch
-            self.pool = concurrent.futures.ThreadPoolExecutor(max(1, max_graphs or 8))
+            self.pool = concurrent.futures.ThreadPoolExecutor(max(1, max_graphs or len(graphs)))
         for n, s, d in graphs:
             stream = None
             if scheme == "each":
                 st = torch.cuda.Stream()
                 self.streams.append(st)
                 stream = dfpr.ctypes.c_void_p(st.cuda_stream)
+            kw = dict(params)
+            if scheme == "each":
+                # graphs are driven from several threads at once: no HIP
+                # graph capture, which other threads' device calls can
+                # invalidate (the library would fall back to launching
+                # the iterations one by one anyway)
+                kw.setdefault("graph_replay", 0)
             g = dfpr.Graph(n, s, d, precision=precision, mode=mode,
-                           renormalize=int(precision == 32), stream=stream, **params)
+                           renormalize=int(precision == 32), stream=stream, **kw)
             g.static()
             self.graphs.append(g)
         self.coalesce = coalesce
@@ -117,28 +132,86 @@ class Server:
         except Exception:
             return 1 << 62
 
+    def _admit(self, rep, pending, queues, t0, open_loop):
+        """Moves arrived requests whose staging fits in free memory to their
+        graphs' queues."""
+        now = time.perf_counter() - t0
+        free = None
+        while pending and (not open_loop or pending[0].arrival <= now):
+            r = pending[0]
+            need = 48 * r.batch.size + self.reserve
+            if free is None:
+                free = self._free_bytes()
+            if need > free:
+                rep.admission_waits += 1
+                break
+            free -= 48 * r.batch.size
+            queues[r.graph].append(pending.popleft())
+
+    def _run_each(self, requests, open_loop: bool) -> Report:
+        import concurrent.futures as cf
+        rep = Report()
+        queues = [collections.deque() for _ in self.graphs]
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        limit = self.max_graphs or len(self.graphs)
+        inflight = {}                      # future -> (graph, requests)
+        t0 = time.perf_counter()
+        done = 0
+
+        def work(i, take):
+            g = self.graphs[i]
+            for r in take:
+                g.apply(r.batch)
+            st = g.update()[1]
+            return st, time.perf_counter() - t0
+
+        while done < len(requests):
+            self._admit(rep, pending, queues, t0, open_loop)
+            busy = {i for i, _ in inflight.values()}
+            idle = [i for i, q in enumerate(queues) if q and i not in busy]
+            idle.sort(key=lambda i: queues[i][0].arrival)
+            for i in idle[:max(0, limit - len(inflight))]:
+                take = [queues[i].popleft()
+                        for _ in range(min(self.coalesce, len(queues[i])))]
+                rep.batch_edges += sum(r.batch.size for r in take)
+                inflight[self.pool.submit(work, i, take)] = (i, take)
+            if not inflight:
+                if pending:
+                    wait = pending[0].arrival - (time.perf_counter() - t0)
+                    if wait > 0:
+                        time.sleep(min(wait, 0.05))
+                continue
+            timeout = None
+            if pending and open_loop:
+                timeout = max(0.0, pending[0].arrival - (time.perf_counter() - t0))
+            fin, _ = cf.wait(list(inflight), timeout=timeout,
+                             return_when=cf.FIRST_COMPLETED)
+            for f in fin:
+                i, take = inflight.pop(f)
+                st, end = f.result()
+                rep.rounds += 1           # one dispatch per graph update
+                rep.updates += 1
+                rep.edges_gathered += st.edges_gathered
+                for r in take:
+                    r.done = end
+                    rep.latencies_ms.append((end - r.arrival) * 1e3)
+                done += len(take)
+        rep.wall_s = time.perf_counter() - t0
+        rep.update_s = rep.wall_s
+        return rep
+
     def run(self, requests, open_loop: bool = True) -> Report:
         """Serves `requests` (sorted by arrival).  open_loop: requests are
         released at their arrival times; otherwise all are available at 0."""
+        if self.scheme == "each":
+            return self._run_each(requests, open_loop)
         rep = Report()
         queues = [collections.deque() for _ in self.graphs]
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
         t0 = time.perf_counter()
         done = 0
         while done < len(requests):
-            now = time.perf_counter() - t0
-            # admission: arrived requests whose staging fits in free memory
-            free = None
-            while pending and (not open_loop or pending[0].arrival <= now):
-                r = pending[0]
-                need = 48 * r.batch.size + self.reserve
-                if free is None:
-                    free = self._free_bytes()
-                if need > free:
-                    rep.admission_waits += 1
-                    break
-                free -= 48 * r.batch.size
-                queues[r.graph].append(pending.popleft())
+            self._admit(rep, pending, queues, t0, open_loop)
             active = [i for i, q in enumerate(queues) if q]
             if self.max_graphs and len(active) > self.max_graphs:
                 # the graphs whose oldest request waits longest go first
@@ -158,22 +231,13 @@ class Server:
                 served.extend(take[i])
                 rep.batch_edges += sum(r.batch.size for r in take[i])
             ta = time.perf_counter()
-            if self.scheme == "batched":
-                for i in active:
-                    for r in take[i]:
-                        self.graphs[i].apply(r.batch)
-                tu = time.perf_counter()
-                rc, stats = dfpr.dfpr_update_many([self.graphs[i].h for i in active])
-                rep.apply_s += tu - ta
-                rep.update_s += time.perf_counter() - tu
-            else:
-                def work(i):
-                    g = self.graphs[i]
-                    for r in take[i]:
-                        g.apply(r.batch)
-                    return g.update()[1]
-                stats = list(self.pool.map(work, active))
-                rep.update_s += time.perf_counter() - ta
+            for i in active:
+                for r in take[i]:
+                    self.graphs[i].apply(r.batch)
+            tu = time.perf_counter()
+            rc, stats = dfpr.dfpr_update_many([self.graphs[i].h for i in active])
+            rep.apply_s += tu - ta
+            rep.update_s += time.perf_counter() - tu
             end = time.perf_counter() - t0
             rep.rounds += 1
             rep.updates += len(active)
