@@ -691,6 +691,34 @@ def test_add_vertices_matches_oracle(D, O, mode, reorder):
     assert err64(R, ref) < FP64_TOL
 
 
+def test_vertices_fp32(D, O):
+    # fp32 ranks: rescaled in fp64 and rounded once; the update after an
+    # insertion and a removal lands within the fp32 bar of the oracle
+    say("vertices fp32")
+    n, s, d = inputs.erdos_renyi(3000, 20000, 6)
+    k = 60
+    R0, _, _ = O.pagerank(n, s, d)
+    rng = np.random.default_rng(23)
+    new = np.arange(n, n + k, dtype=np.int32)
+    old = rng.integers(0, n, k).astype(np.int32)
+    b = inputs.Batch(np.empty(0, np.int32), np.empty(0, np.int32),
+                     np.concatenate([new, old]), np.concatenate([old, new]))
+    ns, nd, res, Rs = O.add_vertices_update(n, s, d, k, b, R0)
+    ref1, _, _ = O.pagerank(n + k, ns, nd)
+    ns2, nd2, _, _ = O.remove_vertices_update(n + k, ns, nd, 2 * k, ref1)
+    ref2, _, _ = O.pagerank(n - k, ns2, nd2)
+    with graph(D, n, s, d, precision=32, renormalize=1) as g:
+        g.set_ranks(R0)
+        g.add_vertices(k)
+        assert rel32(g.ranks(), Rs) < 3e-7          # two fp32 roundings
+        g.apply(b)
+        rc, st = g.update()
+        assert rc == D.DFPR_OK and rel32(g.ranks(), ref1) < FP32_REL
+        g.remove_vertices(2 * k)
+        rc, st = g.update()
+        assert rc == D.DFPR_OK and rel32(g.ranks(), ref2) < FP32_REL
+
+
 @pytest.mark.parametrize("mode", ["sync", "async"])
 def test_remove_vertices_matches_oracle(D, O, mode):
     say("remove vertices", mode)
