@@ -132,9 +132,10 @@ class Server:
         except Exception:
             return 1 << 62
 
-    def _admit(self, rep, pending, queues, t0, open_loop):
+    def _admit(self, rep, pending, queues, t0, open_loop, idle=False):
         """Moves arrived requests whose staging fits in free memory to their
-        graphs' queues."""
+        graphs' queues.  idle: nothing is queued or in flight, so nothing
+        will free memory; the first arrived request is admitted anyway."""
         now = time.perf_counter() - t0
         free = None
         while pending and (not open_loop or pending[0].arrival <= now):
@@ -142,9 +143,10 @@ class Server:
             need = 48 * r.batch.size + self.reserve
             if free is None:
                 free = self._free_bytes()
-            if need > free:
+            if need > free and not idle:
                 rep.admission_waits += 1
                 break
+            idle = False
             free -= 48 * r.batch.size
             queues[r.graph].append(pending.popleft())
 
@@ -166,7 +168,8 @@ class Server:
             return st, time.perf_counter() - t0
 
         while done < len(requests):
-            self._admit(rep, pending, queues, t0, open_loop)
+            self._admit(rep, pending, queues, t0, open_loop,
+                        idle=not inflight and not any(queues))
             busy = {i for i, _ in inflight.values()}
             idle = [i for i, q in enumerate(queues) if q and i not in busy]
             idle.sort(key=lambda i: queues[i][0].arrival)
@@ -211,7 +214,7 @@ class Server:
         t0 = time.perf_counter()
         done = 0
         while done < len(requests):
-            self._admit(rep, pending, queues, t0, open_loop)
+            self._admit(rep, pending, queues, t0, open_loop, idle=not any(queues))
             active = [i for i, q in enumerate(queues) if q]
             if self.max_graphs and len(active) > self.max_graphs:
                 # the graphs whose oldest request waits longest go first
