@@ -2,7 +2,7 @@
  * CPU oracle for Dynamic Frontier PageRank -- TEST INFRASTRUCTURE ONLY.
  *
  * Plain, slow, obviously correct fp64 code that the tests, the smoke check
- * and the benchmark's CPU-baseline leg use to judge the HIP library.  The
+ * and the benchmark's CPU-baseline leg use to check the HIP library.  The
  * product path never links, loads or calls it; it shares no code, header or
  * table with the HIP sources.
  *
