@@ -79,11 +79,17 @@ int grow(dfpr_graph *g, void **p, size_t old_bytes, size_t new_bytes, int fill) 
   hipStream_t s = g->stream;
   void *q = nullptr;
   DFPR_HIP(hipMalloc(&q, new_bytes));
+  hipError_t e = hipSuccess;
   if (old_bytes > 0 && *p)
-    DFPR_HIP(hipMemcpyAsync(q, *p, old_bytes, hipMemcpyDeviceToDevice, s));
-  if (fill >= 0 && new_bytes > old_bytes)
-    DFPR_HIP(hipMemsetAsync(static_cast<char *>(q) + old_bytes, fill, new_bytes - old_bytes, s));
-  DFPR_HIP(hipStreamSynchronize(s));
+    e = hipMemcpyAsync(q, *p, old_bytes, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess && fill >= 0 && new_bytes > old_bytes)
+    e = hipMemsetAsync(static_cast<char *>(q) + old_bytes, fill, new_bytes - old_bytes, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    // the old array stays in place; the new one is given back
+    (void)hipFree(q);
+    return fail(DFPR_EHIP, std::string("growing a per-vertex array: ") + hipGetErrorString(e));
+  }
   if (*p) DFPR_HIP(hipFree(*p));
   *p = q;
   return DFPR_OK;
