@@ -82,10 +82,14 @@ typedef struct {
   int32_t max_iters;     /* cap on sweeps / iterations (500)                */
   int32_t precision;     /* 64: fp64 ranks; 32: fp32 ranks and sums with fp64
                             change tests and norms                          */
-  int32_t mode;          /* DFPR_ASYNC or DFPR_SYNC                         */
+  int32_t mode;          /* DFPR_ASYNC (default, the paper's lock-free
+                            method) or DFPR_SYNC (faster on one MI355X for
+                            large graphs)                                   */
   int32_t kahan_min_degree; /* fp32 ranks: rows with at least this in-degree
-                               accumulate in fp64, shorter rows in fp32    */
-  int32_t split_min_degree; /* barrier-based scheme and static PageRank:
+                               accumulate in fp64, shorter rows in fp32
+                               (default 64)                                */
+  int32_t split_min_degree; /* (default 2048) barrier-based scheme and
+                               static PageRank:
                                rows with at least this in-degree are summed
                                in pieces of 4096 in-edges by whole
                                wavefronts (partial sums added in piece
