@@ -29,8 +29,8 @@
  *    stream).  A call returns after its work on that stream has finished.
  *    One graph must not be used from two threads at once; distinct graphs
  *    are independent.
- *  - Vertex ids are int32 in [0, n); n is fixed for the life of a graph
- *    (no vertex insertion or deletion, Section 3.4).
+ *  - Vertex ids are int32 in [0, n).  Batches keep n fixed (Section 3.4);
+ *    only dfpr_add_vertices and dfpr_remove_vertices change it.
  *  - Every vertex carries an implicit self-loop (dead-end removal,
  *    Section 5.1.3): |out(u)| counts it, and a batch edge (v, v) is ignored.
  */
@@ -61,13 +61,22 @@ extern "C" {
 
 /* scheduling of the rank iteration */
 #define DFPR_ASYNC 0 /* one persistent launch; in-place (Gauss-Seidel-like)
-                        ranks, dynamic grabs of 256-vertex groups, no grid
-                        barrier; ends after a full sweep in which no rank
-                        moved by more than frontier_tol (the lock-free
-                        variant, Algorithm 2)                            */
+                        ranks, dynamic claims of 256-vertex groups and of
+                        4096-edge pieces of long rows, no grid barrier;
+                        ends after a full sweep that meets the lf_stop rule
+                        (the lock-free variant, Algorithm 2)             */
 #define DFPR_SYNC 1  /* one launch per iteration; two rank vectors and an
                         L-infinity norm per iteration (the barrier-based
                         variant, Algorithm 1)                             */
+
+/* stopping rule of the lock-free DF and DT updates (dfpr_params.lf_stop) */
+#define DFPR_STOP_TOL 0      /* a full sweep in which no rank moves by more
+                                than tol: Algorithm 1's test (delta R <= tau)
+                                over the sweeps of the in-place iteration    */
+#define DFPR_STOP_FRONTIER 1 /* a full sweep in which no rank moves by more
+                                than frontier_tol: Algorithm 2's R_C flags
+                                read strictly (every change above tau_f
+                                re-opens its out-neighbours)                 */
 
 /* adjacency directions for dfpr_read_edges */
 #define DFPR_OUT 0
@@ -88,13 +97,13 @@ typedef struct {
   int32_t kahan_min_degree; /* fp32 ranks: rows with at least this in-degree
                                accumulate in fp64, shorter rows in fp32
                                (default 64)                                */
-  int32_t split_min_degree; /* (default 2048) barrier-based scheme and
-                               static PageRank:
-                               rows with at least this in-degree are summed
-                               in pieces of 4096 in-edges by whole
-                               wavefronts (partial sums added in piece
-                               order), the rest in edge-balanced steps of
-                               up to 256 rows                              */
+  int32_t split_min_degree; /* (default 2048) rows with at least this
+                               in-degree are summed in pieces of 4096
+                               in-edges by whole wavefronts (partial sums
+                               added in piece order), the rest in
+                               edge-balanced steps of up to 256 rows; in
+                               the lock-free scheme a row's pieces are
+                               claimed like groups                         */
   int32_t chunk;         /* lock-free scheme: vertices per claim, whole
                             256-vertex groups (chunk / 256, at least one); a
                             multiple of 64 in [64, 4096], or 0 (default):
@@ -128,6 +137,10 @@ typedef struct {
                             launching the iterations one by one; callers
                             that drive graphs from several threads at once
                             are better off with 0                          */
+  int32_t lf_stop;       /* lock-free DF / DT updates: DFPR_STOP_TOL
+                            (default) or DFPR_STOP_FRONTIER.  The lock-free
+                            static and naive-dynamic calls always use the
+                            frontier rule                                   */
 } dfpr_params;
 
 typedef struct {
@@ -284,9 +297,8 @@ int dfpr_mark_reachable(dfpr_graph *g, int64_t *marked);
 /* Dynamic Traversal update (Algorithm 7 in DFPR_SYNC mode, Algorithm 8's
  * lock-free scheme in DFPR_ASYNC mode): dfpr_mark_reachable followed by
  * dfpr_update, timed together in stats->ms; stats->initial_marked is the
- * size of the reachable set.  The lock-free scheme ends after a full sweep
- * that moves no vertex by more than frontier_tol, as the lock-free static
- * and naive-dynamic calls do.  Same returns as dfpr_update. */
+ * size of the reachable set.  The lock-free scheme ends by the lf_stop
+ * rule, as the lock-free DF update does.  Same returns as dfpr_update. */
 int dfpr_update_traversal(dfpr_graph *g, dfpr_stats *stats);
 
 /* Dynamic Frontier updates of `count` graphs in one persistent launch

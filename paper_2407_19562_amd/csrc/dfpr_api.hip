@@ -69,6 +69,8 @@ int check_params(const dfpr_params *p) {
     return fail(DFPR_EINVAL, "grid_blocks * waves per block must be <= 32768");
   if (p->graph_replay < 0 || p->graph_replay > 2)
     return fail(DFPR_EINVAL, "graph_replay must be 0, 1 or 2");
+  if (p->lf_stop != DFPR_STOP_TOL && p->lf_stop != DFPR_STOP_FRONTIER)
+    return fail(DFPR_EINVAL, "lf_stop must be DFPR_STOP_TOL or DFPR_STOP_FRONTIER");
   return DFPR_OK;
 }
 
@@ -82,7 +84,7 @@ static void release(dfpr_graph *g) {
                   g->sync_grab, g->sync_len, g->gflags, g->gwl,
                   g->ext2int, g->int2ext, g->steps,
                   g->split.lrow, g->split.lpre, g->split.lcnt, g->split.prow,
-                  g->split.ppart, g->split.xrow, g->tiles, g->faults};
+                  g->split.ppart, g->split.ptag, g->split.xrow, g->tiles, g->faults};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (auto &s : g->scratch)
@@ -125,6 +127,7 @@ static int alloc_graph(dfpr_graph *g) {
   DFPR_HIP(hipMemsetAsync(g->gflags, 0, gbytes, g->stream));
   DFPR_HIP(hipMalloc(&g->gwl, (size_t)g->ngroups * 4));
   DFPR_HIP(hipMemsetAsync(g->gwl, 0xFF, (size_t)g->ngroups * 4, g->stream));
+  g->gwl_cap = g->ngroups;  // ensure_split adds room for the pieces
   DFPR_HIP(hipMalloc(&g->ctl, sizeof(Ctl)));
   DFPR_HIP(hipMemsetAsync(g->ctl, 0, sizeof(Ctl), g->stream));
   DFPR_HIP(hipHostMalloc(&g->h_ctl, sizeof(Ctl), hipHostMallocDefault));
@@ -180,6 +183,7 @@ int dfpr_params_default(dfpr_params *p) {
   p->timeout_ms = 60000;
   p->grid_blocks = 0;
   p->graph_replay = 2;
+  p->lf_stop = DFPR_STOP_TOL;
   return DFPR_OK;
 }
 
@@ -230,7 +234,7 @@ int dfpr_graph_create(int32_t n, int64_t m, const int32_t *src,
     release(g);
     return rc;
   }
-  if ((rc = init_uniform_ranks(g))) {
+  if ((rc = init_uniform_ranks(g)) || (rc = ensure_split(g))) {
     release(g);
     return rc;
   }
@@ -259,7 +263,9 @@ int dfpr_set_params(dfpr_graph *g, const dfpr_params *p) {
   if (p->precision != g->p.precision)
     return fail(DFPR_EINVAL, "precision is fixed at graph creation");
   g->p = *p;
-  return DFPR_OK;
+  // piece arrays sized for the (possibly lower) split threshold now, not in
+  // the next update
+  return ensure_split(g);
 }
 
 int dfpr_get_params(const dfpr_graph *g, dfpr_params *p) {

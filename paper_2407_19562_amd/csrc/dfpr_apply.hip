@@ -641,6 +641,8 @@ int apply_batch(dfpr_graph *g, int64_t nd, const int32_t *ds,
     return fail(DFPR_EHIP, "in/out adjacency disagree after the batch");
   g->m += (int64_t)h.ins_applied - (int64_t)h.del_applied;
   g->pending_marks = (int64_t)h.marked;
+  // piece arrays follow adjacency growth here, so updates allocate nothing
+  if (int rc = ensure_split(g)) return rc;
   if (applied_del) *applied_del = (int64_t)h.del_applied;
   if (applied_ins) *applied_ins = (int64_t)h.ins_applied;
   return DFPR_OK;

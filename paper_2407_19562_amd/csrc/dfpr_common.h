@@ -81,8 +81,9 @@ struct Ctl {
   unsigned long long nlong_del;           // apply: long rows with deletions
   unsigned long long nlong_mark;          // apply: long out-rows to mark
   alignas(128) unsigned long long gtail;  // group worklist length
-  alignas(128) long long change_sweep;    // last sweep in which a claim saw a
-                                          // change above the frontier tol
+  alignas(128) long long change_sweep;    // last sweep in which a claim saw
+                                          // a change above the watermark
+                                          // tolerance or affected a vertex
   alignas(128) int abort;                 // watchdog fired
   alignas(128) long long marked;          // vertices affected by the marking
   long long newly;                        // vertices affected during the update
@@ -112,18 +113,24 @@ struct Adj {
   int64_t adj_cap = 0;  // slots allocated in adj
 };
 
-// Rows gathered in pieces (barrier-based scheme and static PageRank): a
-// worklist row whose in-degree reaches split_min_degree is cut into pieces
-// of kPiece in-edges.  Whole wavefronts sum one piece each; the wavefront
-// that finishes a row's last piece adds the partial sums in piece order and
-// completes the vertex.
+// Rows gathered in pieces (both schemes and static PageRank): a row whose
+// in-degree reaches split_min_degree is cut into pieces of kPiece
+// in-edges.  Whole wavefronts sum one piece each; the wavefront that
+// finishes a row's last piece adds the partial sums in piece order and
+// completes the vertex.  Barrier-based scheme: the rows are rebuilt from
+// the affected flags every iteration.  Lock-free scheme: a row is listed
+// when it becomes affected, and its pieces join the group worklist as
+// entries -(p + 2).
 constexpr int kPiece = 4096;
 struct Split {
   int32_t *lrow = nullptr;  // [lcap] vertex of long row j
   int32_t *lpre = nullptr;  // [lcap + 1] first piece of long row j
-  int32_t *lcnt = nullptr;  // [lcap] pieces of row j finished (the last resets it)
+  int32_t *lcnt = nullptr;  // [lcap] pieces of row j finished (barrier-based:
+                            // the last resets it; lock-free: counts on)
   int32_t *prow = nullptr;  // [pcap] long row of piece p
   double *ppart = nullptr;  // [pcap] partial sum of piece p
+  int32_t *ptag = nullptr;  // [pcap] lock-free scheme: launch that last wrote
+                            // ppart[p]
   int32_t *xrow = nullptr;  // [xcap] vertices whose long out-rows are marked
                             // after the iteration (Ctl::nexp entries)
   int64_t lcap = 0, pcap = 0, xcap = 0;
@@ -161,7 +168,12 @@ struct dfpr_graph {
   int32_t *wl = nullptr;
   int32_t ngroups = 0;
   uint32_t *gflags = nullptr;  // [ngroups] bytes
-  int32_t *gwl = nullptr;      // group worklist [ngroups], unused slots -1
+  int32_t *gwl = nullptr;      // group worklist of the lock-free scheme, with
+                               // the pieces of its long rows
+                               // [gwl_cap >= ngroups + split.pcap], unused
+                               // slots -1
+  int64_t gwl_cap = 0;
+  int32_t async_epoch = 0;     // lock-free launches so far (piece tags)
   int32_t *steps = nullptr;    // step starts over the worklist [n + 1]
   void *tiles = nullptr;       // per-tile sums and their prefixes
                                // [2 * (n / 256 + 2)] x 16 bytes
@@ -227,6 +239,9 @@ int add_vertices(dfpr_graph *g, int32_t count, int32_t *first_id);
 int remove_vertices(dfpr_graph *g, int32_t count);
 
 // Ranks (dfpr_rank.hip).
+// Sizes the piece arrays and the group worklist for the current adjacency
+// capacities and split threshold (allocates only when they grew).
+int ensure_split(dfpr_graph *g);
 int init_uniform_ranks(dfpr_graph *g);
 int refresh_contributions(dfpr_graph *g);
 

@@ -10,10 +10,9 @@
 //          and adds them to the owning row's LDS accumulator.  The implicit
 //          self-loop adds C[v].
 //   piece  up to kPiece consecutive in-edges of one long row (in-degree at
-//          or above split_min_degree; barrier-based scheme and static
-//          PageRank only), summed by a whole wavefront in registers; the
-//          wavefront completing the row's last piece adds the partial sums
-//          in piece order and finishes the vertex.
+//          or above split_min_degree), summed by a whole wavefront in
+//          registers; the wavefront completing the row's last piece adds
+//          the partial sums in piece order and finishes the vertex.
 //   finish r = (1 - alpha)/n + alpha * sum, dr = |r - R[v]|; when dr exceeds
 //          the frontier tolerance every out-neighbour is marked affected
 //          (once per vertex and update: flag bit kEX).
@@ -22,10 +21,12 @@
 //   k_df_async   one persistent launch (lock-free scheme, Algorithm 2).  A
 //                64-bit word holds the sweep index, a cursor into the group
 //                worklist and the number of claims in flight; wavefronts
-//                claim groups with fetch_add and recompute their affected
-//                vertices in place.  A sweep ends the update when no claim
-//                is held and no claim of that sweep saw a change above the
-//                frontier tolerance (change_sweep watermark).  No grid
+//                claim worklist entries with fetch_add (256-vertex groups,
+//                whose affected vertices they recompute in place, and the
+//                pieces of affected long rows).  A sweep ends the update
+//                when no claim is held and no claim completed during that
+//                sweep saw a rank change above the iteration tolerance or
+//                affected a new vertex (change_sweep watermark).  No grid
 //                barrier anywhere: sweeps overlap.
 //   k_sync_iter  one launch per iteration reading R/C and writing the other
 //                buffer (Algorithm 1): wavefronts claim the iteration's
@@ -66,16 +67,20 @@ struct RankArgs {
   int32_t *gwl;
   Ctl *ctl;
   double alpha, base, tol, ftol;
+  double wtol;  // lock-free scheme: a claim with a rank change above wtol
+                // (or a newly affected vertex) forces another sweep
   int32_t split_min, kahan_min, chunk, max_iters;
   unsigned long long timeout_ticks;
   unsigned long long *sync_max;
   unsigned long long *sync_grab;
   unsigned long long *sync_len;  // per iteration: steps | pieces << 32
-  const int32_t *lrow;           // rows gathered in pieces (Split)
-  const int32_t *lpre;
-  const int32_t *prow;
+  int32_t *lrow;                 // rows gathered in pieces (Split)
+  int32_t *lpre;
+  int32_t *prow;
   double *ppart;
   int32_t *lcnt;
+  int32_t *ptag;                 // lock-free: launch that wrote ppart[p]
+  int32_t epoch;                 // lock-free: this launch
   int32_t *xrow;                 // deferred long out-rows (Split)
   const int32_t *faults;         // injected faults per workgroup (or null)
   int32_t nfaults;
@@ -263,6 +268,28 @@ __device__ __forceinline__ void gather_flat(const RankArgs<T> &A, WaveLds<T> &L,
   }
 }
 
+// Lock-free scheme: lists long row v (in-degree d >= split_min, just
+// affected) with its pieces, and appends the pieces to the group worklist
+// as entries -(p + 2).  One lane; rare (a row is listed once per update).
+__device__ __forceinline__ void list_long_row(Ctl *ctl, int32_t *lrow, int32_t *lpre,
+                                              int32_t *lcnt, int32_t *prow, int32_t *gwl,
+                                              int32_t v, int32_t d) {
+  const int32_t np = (d + kPiece - 1) / kPiece;
+  const unsigned long long j = __hip_atomic_fetch_add(&ctl->nlong, 1ull, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+  const unsigned long long p0 = __hip_atomic_fetch_add(
+      &ctl->npieces, (unsigned long long)np, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  store_agent(lrow + j, v);
+  store_agent(lpre + j, (int32_t)p0);
+  store_agent(lcnt + j, 0);
+  for (int32_t k = 0; k < np; ++k) store_agent(prow + p0 + k, (int32_t)j);
+  // the row's table is in place before a claim can read one of its pieces
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  const unsigned long long pos = __hip_atomic_fetch_add(
+      &ctl->gtail, (unsigned long long)np, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int32_t k = 0; k < np; ++k) store_agent(gwl + pos + k, -(int32_t)(p0 + k) - 2);
+}
+
 // Synchronous scheme: marks w affected; true when w is newly affected.
 __device__ __forceinline__ bool mark_vertex_sync(uint32_t *flags, int32_t w) {
   if (flag_byte(flags, w, false) & kVA) return false;
@@ -300,6 +327,12 @@ __device__ __forceinline__ void expand_flat(const RankArgs<T> &A, WaveLds<T> &L,
         if (w[j] >= 0) o = mark_affected(A.flags, A.gflags, w[j]);
         newly += o.vnew ? 1 : 0;
         wave_append(o.gnew, o.g, A.gwl, &A.ctl->gtail, true);
+        if (o.vnew) {
+          // a long row joins the worklist as pieces (its group skips it)
+          const int32_t dw = A.in_deg[w[j]];
+          if (dw >= A.split_min)
+            list_long_row(A.ctl, A.lrow, A.lpre, A.lcnt, A.prow, A.gwl, w[j], dw);
+        }
       } else {
         if (w[j] >= 0 && mark_vertex_sync(A.flags, w[j])) ++newly;
       }
@@ -347,9 +380,18 @@ __device__ __forceinline__ void finish_rows(const RankArgs<T> &A, WaveLds<T> &L,
     cnt.vertices += 1;
     cnt.edges += (unsigned long long)deg[k] + 1;
     maxdr = dr > maxdr ? dr : maxdr;
+    // fp32 ranks: a change of one unit in the last place is rounding noise
+    // of the unordered sums, never a reason for another sweep (a rank of
+    // 1e-2 has ulp 9e-10, above the iteration tolerance)
+    double wt = A.wtol;
+    if constexpr (sizeof(T) == 4) {
+      const float ar = fabsf((float)rT);
+      const double ulp = (double)__uint_as_float(__float_as_uint(ar) + 1u) - (double)ar;
+      wt = ulp > wt ? ulp : wt;
+    }
+    if (dr > wt) moved = true;
     if constexpr (MODE != kAll) {
       if (dr > A.ftol) {
-        moved = true;
         // a vertex that already marked all its out-neighbours has nothing
         // left to mark: affected flags are never cleared within an update
         if (!(flag_byte(A.flags, x, COH) & kEX)) {
@@ -378,9 +420,9 @@ __device__ __forceinline__ void finish_rows(const RankArgs<T> &A, WaveLds<T> &L,
 
 // Processes one step: four vertices per lane (vin[k] < 0: empty slot).  All
 // 64 lanes call it.  `moved` is set when a rank changed by more than the
-// frontier tolerance; `maxdr` tracks the largest change.  Outside the
-// lock-free scheme, rows with at least split_min in-edges are left to the
-// piece path.
+// watermark tolerance (lock-free scheme); `maxdr` tracks the largest
+// change.  Rows with at least split_min in-edges are left to the piece
+// path.
 template <typename T, int MODE>
 __device__ __forceinline__ void process_step(const RankArgs<T> &A, WaveLds<T> &L,
                                              const int32_t *vin, Counters &cnt,
@@ -397,7 +439,7 @@ __device__ __forceinline__ void process_step(const RankArgs<T> &A, WaveLds<T> &L
     deg[k] = 0;
     if (v[k] >= 0) {
       const int32_t d = A.in_deg[v[k]];
-      if (MODE != kAsync && d >= A.split_min) {
+      if (d >= A.split_min) {
         v[k] = -1;
       } else {
         off[k] = A.in_off[v[k]];
@@ -410,22 +452,30 @@ __device__ __forceinline__ void process_step(const RankArgs<T> &A, WaveLds<T> &L
   finish_rows<T, MODE>(A, L, v, deg, sum, cnt, maxdr, newly, moved);
 }
 
-// One piece of a long row (barrier-based scheme, static PageRank): the
-// wavefront sums up to kPiece consecutive in-edges of the row in registers
-// (fp64 for both rank types) and publishes the partial sum; the wavefront
-// that completes the row's last piece adds the row's partial sums in piece
-// order (so the result does not depend on which piece finished when) and
-// finishes the vertex.
+// One piece of a long row: the wavefront sums up to kPiece consecutive
+// in-edges of the row in registers (fp64 for both rank types) and publishes
+// the partial sum; the wavefront that completes the row's last piece adds
+// the row's partial sums in piece order (so the result does not depend on
+// which piece finished when) and finishes the vertex.
+//   barrier-based scheme, static PageRank: every piece of the row is summed
+//     once per iteration, and the finishing wavefront resets the counter;
+//   lock-free scheme: sweeps overlap, so a piece can be summed again before
+//     a slow piece of the previous sweep is in.  The counter runs on, and
+//     every np-th completion finishes the vertex from the latest partial
+//     sums, provided each piece was summed during this launch (tagged with
+//     the launch); otherwise `moved` forces another sweep.
 template <typename T, int MODE>
 __device__ void process_piece(const RankArgs<T> &A, WaveLds<T> &L, int32_t p,
                               Counters &cnt, double &maxdr, long long &newly,
                               bool &moved) {
+  constexpr bool COH = MODE == kAsync;
   const int lane = lane_id();
-  const int32_t j = __builtin_amdgcn_readfirstlane(A.prow[p]);
-  const int32_t v = __builtin_amdgcn_readfirstlane(A.lrow[j]);
-  const int32_t first = __builtin_amdgcn_readfirstlane(A.lpre[j]);
-  const int32_t np = __builtin_amdgcn_readfirstlane(A.lpre[j + 1]) - first;
+  const int32_t j = __builtin_amdgcn_readfirstlane(COH ? load_agent(A.prow + p) : A.prow[p]);
+  const int32_t v = __builtin_amdgcn_readfirstlane(COH ? load_agent(A.lrow + j) : A.lrow[j]);
+  const int32_t first =
+      __builtin_amdgcn_readfirstlane(COH ? load_agent(A.lpre + j) : A.lpre[j]);
   const int32_t d = __builtin_amdgcn_readfirstlane(A.in_deg[v]);
+  const int32_t np = (d + kPiece - 1) / kPiece;
   const int32_t *row = A.in_adj + A.in_off[v];
   const int32_t a = (p - first) * kPiece;
   const int32_t b = a + kPiece < d ? a + kPiece : d;
@@ -445,7 +495,7 @@ __device__ void process_piece(const RankArgs<T> &A, WaveLds<T> &L, int32_t p,
   for (int32_t e0 = a; e0 < b; e0 += kUnroll * kWave) {
     T c[kUnroll];
 #pragma unroll
-    for (int q = 0; q < kUnroll; ++q) c[q] = A.Cr[idx[q]];
+    for (int q = 0; q < kUnroll; ++q) c[q] = ldc<T, COH>(A.Cr, idx[q]);
     const int32_t next = e0 + kUnroll * kWave;
     if (next < b) fetch(next);
 #pragma unroll
@@ -459,17 +509,29 @@ __device__ void process_piece(const RankArgs<T> &A, WaveLds<T> &L, int32_t p,
     int last = 0;
     if (lane == 0) {
       store_agent(A.ppart + p, part);
+      if (COH) store_agent(A.ptag + p, A.epoch);
       const int32_t before = __hip_atomic_fetch_add(A.lcnt + j, 1, __ATOMIC_ACQ_REL,
                                                     __HIP_MEMORY_SCOPE_AGENT);
-      last = before == np - 1;
+      last = COH ? (before + 1) % np == 0 : before == np - 1;
     }
     if (!__builtin_amdgcn_readfirstlane(last)) return;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if constexpr (COH) {
+      bool have = true;
+      for (int32_t k = lane; k < np; k += kWave)
+        have = have && load_agent(A.ptag + first + k) == A.epoch;
+      if (__ballot(!have) != 0) {
+        moved = true;  // a piece not yet summed in this launch: next sweep
+        return;
+      }
+    }
+    // fixed order: lane k adds pieces k, k + 64, ..., then the wave sum
     double t = 0.0;
     for (int32_t k = lane; k < np; k += kWave) t += load_agent(A.ppart + first + k);
     total = wave_sum(t);
-    // every piece of the row has arrived: ready for the next iteration
-    if (lane == 0) store_agent(A.lcnt + j, 0);
+    // barrier-based: every piece of the row has arrived, ready for the next
+    // iteration
+    if (!COH && lane == 0) store_agent(A.lcnt + j, 0);
   }
   int32_t vv[kQ];
   int32_t dd[kQ];
@@ -498,15 +560,17 @@ __device__ __forceinline__ void flush_counters(Ctl *ctl, Counters &c) {
 // Sweep-end decision, lane 0 only, on a state word W read with a relaxed
 // load whose cursor reached the end of the group worklist.
 //
-// Convergence: every claim that saw a rank change above the frontier
-// tolerance raises change_sweep to the sweep index current when it
-// finishes (a returning atomic, performed before the claim drops its
-// in-flight mark).  Sweep S may end the launch only when no claim is held
-// and change_sweep < S: then every group was recomputed in S from ranks
-// that no later change above the frontier tolerance has touched, and no
-// vertex moved by more than that in S.  In Algorithm 2's terms every R_C
-// is 0 and no change is left to propagate.  Otherwise the next sweep
-// starts at once, without waiting for claims still held (no barrier).
+// Convergence (Algorithm 2's R_C flags, kept per claim): a claim that saw
+// a rank change above the watermark tolerance wtol (the iteration
+// tolerance for DF updates), affected a new vertex, or met an entry it
+// could not finish raises change_sweep to the sweep index current when it
+// completes (a returning atomic after a release fence, performed before
+// the claim drops its in-flight mark).  Sweep S may end the launch only
+// when no claim is held and change_sweep < S: then every worklist entry was
+// processed during S, no rank moved by more than wtol and no vertex became
+// affected, so every R_C is 0 and every affected vertex has been
+// recomputed.  Otherwise the next sweep starts at once, without waiting for
+// claims still held (no barrier).
 template <typename T>
 __device__ void sweep_end(const RankArgs<T> &A, unsigned long long W,
                           int *done_count) {
@@ -541,8 +605,8 @@ __device__ void sweep_end(const RankArgs<T> &A, unsigned long long W,
 enum StepResult { kWorked = 0, kNoWork = 1, kGraphDone = 2 };
 
 // One scheduling step of the lock-free scheme on one graph: claim
-// `per` positions of its group worklist and recompute every affected vertex
-// of those groups in place.  A graph never gets more claim holders than it
+// `per` positions of its group worklist and process them in place (the
+// affected vertices of a group, or a piece of an affected long row).  A graph never gets more claim holders than it
 // has listed groups; beyond that, extra wavefronts would only start new
 // sweeps over groups still being processed.
 template <typename T>
@@ -584,21 +648,34 @@ __device__ int df_async_step(const RankArgs<T> &A, WaveLds<T> &L, Counters &cnt,
   bool moved = false;
   double unused = 0.0;
   for (unsigned long long gp = p; gp < end; ++gp) {
-    int32_t grp = -1;
-    if (lane == 0) grp = load_agent(A.gwl + gp);
-    grp = __builtin_amdgcn_readfirstlane(grp);
-    if (grp < 0) continue;  // slot reserved, id not yet stored
-    const int32_t v0 = grp << kGroupShift;
+    int32_t x = -1;
+    if (lane == 0) x = load_agent(A.gwl + gp);
+    x = __builtin_amdgcn_readfirstlane(x);
+    if (x == -1) {
+      // slot reserved, entry not yet stored: its appender's claim raises
+      // the watermark; count it as work left all the same
+      moved = true;
+      continue;
+    }
+    if (x <= -2) {  // a piece of an affected long row
+      process_piece<T, kAsync>(A, L, -x - 2, cnt, unused, newly, moved);
+      continue;
+    }
+    const int32_t v0 = x << kGroupShift;
     int32_t vv[kQ];
 #pragma unroll
     for (int k = 0; k < kQ; ++k) {
-      const int32_t x = v0 + k * kWave + lane;
-      vv[k] = (x < A.n && (flag_byte(A.flags, x, true) & kVA)) ? x : -1;
+      const int32_t v = v0 + k * kWave + lane;
+      vv[k] = (v < A.n && (flag_byte(A.flags, v, true) & kVA)) ? v : -1;
     }
     process_step<T, kAsync>(A, L, vv, cnt, unused, newly, moved);
   }
   const bool any = __ballot(moved) != 0;
   if (lane == 0) {
+    // every store of this claim (ranks, contributions, flags, worklist
+    // entries) is performed before the watermark and the in-flight count
+    // change: a sweep that ends the launch sees them
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     long long seen = 0;
     if (any) {
       // the sweep current now (not the claim's): changes made late in an
@@ -914,6 +991,9 @@ __global__ void k_async_begin(Ctl *ctl) {
   ctl->state = 0ull;
   ctl->newly = 0;
   ctl->change_sweep = -1;
+  ctl->gtail = 0;
+  ctl->nlong = 0;
+  ctl->npieces = 0;
   ctl->vertices = ctl->edges = ctl->out_scanned = 0;
   ctl->abort = 0;
 }
@@ -979,6 +1059,9 @@ __global__ void k_begin_many(const RankArgs<T> *descs, int count, int *done_coun
     c->state = 0ull;
     c->newly = 0;
     c->change_sweep = -1;
+    c->gtail = 0;
+    c->nlong = 0;
+    c->npieces = 0;
     c->abort = 0;
     c->vertices = c->edges = c->out_scanned = 0;
   }
@@ -991,7 +1074,8 @@ __global__ void k_cleanup_many(const RankArgs<T> *descs, int count) {
   for (int i = blockIdx.x; i < count; i += gridDim.x) {
     const RankArgs<T> &A = descs[i];
     Ctl *c = A.ctl;
-    const unsigned long long len = c->tail, glen = c->gtail;
+    const unsigned long long len = c->tail, glen = c->gtail, nl = c->nlong;
+    for (unsigned long long k = threadIdx.x; k < nl; k += blockDim.x) A.lcnt[k] = 0;
     for (unsigned long long k = threadIdx.x; k < len; k += blockDim.x) {
       const int32_t v = A.wl[k];
       if (v >= 0) reinterpret_cast<uint8_t *>(A.flags)[v] = 0;
@@ -1178,6 +1262,7 @@ RankArgs<T> make_args(dfpr_graph *g, int rd, int wr) {
   A.base = (1.0 - g->p.alpha) / (double)g->n;
   A.tol = g->p.tol;
   A.ftol = g->p.frontier_tol;
+  A.wtol = g->p.lf_stop == DFPR_STOP_FRONTIER ? g->p.frontier_tol : g->p.tol;
   A.split_min = g->p.split_min_degree;
   A.kahan_min = g->p.kahan_min_degree;
   A.chunk = effective_chunk(g);
@@ -1193,6 +1278,8 @@ RankArgs<T> make_args(dfpr_graph *g, int rd, int wr) {
   A.prow = g->split.prow;
   A.ppart = g->split.ppart;
   A.lcnt = g->split.lcnt;
+  A.ptag = g->split.ptag;
+  A.epoch = g->async_epoch;
   A.xrow = g->split.xrow;
   A.faults = g->faults;
   A.nfaults = g->nfaults;
@@ -1435,11 +1522,12 @@ __global__ void __launch_bounds__(256) k_tile_emit(const uint32_t *flags,
 
 // Group worklist of the lock-free scheme from the listed flags: one
 // 256-thread workgroup per graph compacts the graph's group flags in id
-// order into gwl and sets gtail.
+// order into gwl after the entries already there (the pieces of the long
+// rows, k_list_long) and sets gtail.
 __device__ __forceinline__ void list_groups(const uint8_t *gflags, int32_t ngroups,
                                             int32_t *gwl, unsigned long long *gtail) {
   __shared__ int32_t lds4[4];
-  int32_t base = 0;
+  int32_t base = (int32_t)*gtail;
   for (int32_t g0 = 0; g0 < ngroups; g0 += kRows) {
     const int32_t gi = g0 + (int32_t)threadIdx.x;
     const bool sel = gi < ngroups && (gflags[gi] & kGA);
@@ -1448,7 +1536,49 @@ __device__ __forceinline__ void list_groups(const uint8_t *gflags, int32_t ngrou
     if (sel) gwl[base + pos] = gi;
     base += total;
   }
+  __syncthreads();  // every thread has read *gtail
   if (threadIdx.x == 0) *gtail = (unsigned long long)base;
+}
+
+// Lock-free scheme, at launch: every affected long row is listed with its
+// pieces at the head of the group worklist, so the long chains start
+// first.  Rows that become affected during the update are listed by the
+// frontier expansion.
+__device__ __forceinline__ void list_long_rows(const uint32_t *flags, const int32_t *deg,
+                                               int32_t n, int32_t split, int64_t v0,
+                                               int64_t stride, Ctl *ctl, int32_t *lrow,
+                                               int32_t *lpre, int32_t *lcnt,
+                                               int32_t *prow, int32_t *gwl) {
+  for (int64_t v = v0; v < n; v += stride) {
+    if (!(reinterpret_cast<const uint8_t *>(flags)[v] & kVA)) continue;
+    const int32_t d = deg[v];
+    if (d >= split) list_long_row(ctl, lrow, lpre, lcnt, prow, gwl, (int32_t)v, d);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_list_long(const uint32_t *flags, const int32_t *deg,
+                                                   int32_t n, int32_t split, Ctl *ctl,
+                                                   Split S, int32_t *gwl) {
+  list_long_rows(flags, deg, n, split, blockIdx.x * (int64_t)blockDim.x + threadIdx.x,
+                 (int64_t)gridDim.x * blockDim.x, ctl, S.lrow, S.lpre, S.lcnt, S.prow, gwl);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_list_long_many(const RankArgs<T> *descs, int count) {
+  for (int i = blockIdx.x; i < count; i += gridDim.x) {
+    const RankArgs<T> &A = descs[i];
+    list_long_rows(A.flags, A.in_deg, A.n, A.split_min, threadIdx.x, blockDim.x, A.ctl, A.lrow,
+                   A.lpre, A.lcnt, A.prow, A.gwl);
+  }
+}
+
+// After a lock-free launch: the piece counters of its long rows back to 0
+// (the barrier-based scheme counts each iteration from 0).
+__global__ void k_zero_lcnt(int32_t *lcnt, const Ctl *ctl) {
+  const unsigned long long nl = ctl->nlong;
+  for (unsigned long long j = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; j < nl;
+       j += (unsigned long long)gridDim.x * blockDim.x)
+    lcnt[j] = 0;
 }
 
 __global__ void __launch_bounds__(256) k_list_groups(const uint32_t *gflags, int32_t ngroups,
@@ -1470,37 +1600,6 @@ __global__ void k_zero_bytes(uint32_t *p, int64_t words) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words;
        i += (int64_t)gridDim.x * blockDim.x)
     p[i] = 0u;
-}
-
-// Sizes the piece arrays for the current adjacency capacities and
-// threshold: a row with at least split_min entries holds that many slots,
-// so at most adj_cap / split_min in-rows are long (with at most
-// adj_cap / kPiece + (long rows) pieces), and at most out adj_cap /
-// split_min out-rows can be deferred in one iteration.
-int ensure_split(dfpr_graph *g) {
-  Split &S = g->split;
-  int64_t lcap = g->in.adj_cap / g->p.split_min_degree + 1;
-  if (lcap > (int64_t)g->n + 1) lcap = (int64_t)g->n + 1;
-  const int64_t pcap = g->in.adj_cap / kPiece + lcap + 1;
-  int64_t xcap = g->out.adj_cap / g->p.split_min_degree + 1;
-  if (xcap > (int64_t)g->n + 1) xcap = (int64_t)g->n + 1;
-  if (lcap <= S.lcap && pcap <= S.pcap && xcap <= S.xcap) return DFPR_OK;
-  DFPR_HIP(hipStreamSynchronize(g->stream));
-  void *old[] = {S.lrow, S.lpre, S.lcnt, S.prow, S.ppart, S.xrow};
-  for (void *p : old)
-    if (p) DFPR_HIP(hipFree(p));
-  S = Split();
-  DFPR_HIP(hipMalloc(&S.lrow, (size_t)lcap * 4));
-  DFPR_HIP(hipMalloc(&S.lpre, (size_t)(lcap + 1) * 4));
-  DFPR_HIP(hipMalloc(&S.lcnt, (size_t)lcap * 4));
-  DFPR_HIP(hipMalloc(&S.prow, (size_t)pcap * 4));
-  DFPR_HIP(hipMalloc(&S.ppart, (size_t)pcap * 8));
-  DFPR_HIP(hipMalloc(&S.xrow, (size_t)xcap * 4));
-  DFPR_HIP(hipMemsetAsync(S.lcnt, 0, (size_t)lcap * 4, g->stream));
-  S.lcap = lcap;
-  S.pcap = pcap;
-  S.xcap = xcap;
-  return DFPR_OK;
 }
 
 // Exclusive scan of nt1 tile sums by one workgroup (whole wavefronts, at
@@ -1786,6 +1885,67 @@ int run_sync(dfpr_graph *g, int mode, dfpr_stats *st) {
   return h.sync_conv ? DFPR_OK : DFPR_NOTCONVERGED;
 }
 
+}  // namespace
+
+// Sizes the piece arrays for the current adjacency capacities and
+// threshold: a row with at least split_min entries holds that many slots,
+// so at most adj_cap / split_min in-rows are long (with at most
+// adj_cap / kPiece + (long rows) pieces), and at most out adj_cap /
+// split_min out-rows can be deferred in one iteration.  The lock-free
+// scheme's worklist holds every group and every piece.
+int ensure_split(dfpr_graph *g) {
+  Split &S = g->split;
+  int64_t lcap = g->in.adj_cap / g->p.split_min_degree + 1;
+  if (lcap > (int64_t)g->n + 1) lcap = (int64_t)g->n + 1;
+  const int64_t pcap = g->in.adj_cap / kPiece + lcap + 1;
+  int64_t xcap = g->out.adj_cap / g->p.split_min_degree + 1;
+  if (xcap > (int64_t)g->n + 1) xcap = (int64_t)g->n + 1;
+  if (lcap > S.lcap || pcap > S.pcap || xcap > S.xcap) {
+    DFPR_HIP(hipStreamSynchronize(g->stream));
+    void *old[] = {S.lrow, S.lpre, S.lcnt, S.prow, S.ppart, S.ptag, S.xrow};
+    for (void *p : old)
+      if (p) DFPR_HIP(hipFree(p));
+    S = Split();
+    DFPR_HIP(hipMalloc(&S.lrow, (size_t)lcap * 4));
+    DFPR_HIP(hipMalloc(&S.lpre, (size_t)(lcap + 1) * 4));
+    DFPR_HIP(hipMalloc(&S.lcnt, (size_t)lcap * 4));
+    DFPR_HIP(hipMalloc(&S.prow, (size_t)pcap * 4));
+    DFPR_HIP(hipMalloc(&S.ppart, (size_t)pcap * 8));
+    DFPR_HIP(hipMalloc(&S.ptag, (size_t)pcap * 4));
+    DFPR_HIP(hipMalloc(&S.xrow, (size_t)xcap * 4));
+    DFPR_HIP(hipMemsetAsync(S.lcnt, 0, (size_t)lcap * 4, g->stream));
+    DFPR_HIP(hipMemsetAsync(S.ptag, 0, (size_t)pcap * 4, g->stream));
+    S.lcap = lcap;
+    S.pcap = pcap;
+    S.xcap = xcap;
+  }
+  const int64_t gneed = (int64_t)g->ngroups + S.pcap;
+  if (gneed > g->gwl_cap) {
+    DFPR_HIP(hipStreamSynchronize(g->stream));
+    if (g->gwl) DFPR_HIP(hipFree(g->gwl));
+    g->gwl = nullptr;
+    g->gwl_cap = 0;
+    DFPR_HIP(hipMalloc(&g->gwl, (size_t)gneed * 4));
+    DFPR_HIP(hipMemsetAsync(g->gwl, 0xFF, (size_t)gneed * 4, g->stream));
+    g->gwl_cap = gneed;
+  }
+  return DFPR_OK;
+}
+
+// True when ensure_split would allocate nothing.
+bool split_ready(const dfpr_graph *g) {
+  const Split &S = g->split;
+  int64_t lcap = g->in.adj_cap / g->p.split_min_degree + 1;
+  if (lcap > (int64_t)g->n + 1) lcap = (int64_t)g->n + 1;
+  const int64_t pcap = g->in.adj_cap / kPiece + lcap + 1;
+  int64_t xcap = g->out.adj_cap / g->p.split_min_degree + 1;
+  if (xcap > (int64_t)g->n + 1) xcap = (int64_t)g->n + 1;
+  return lcap <= S.lcap && pcap <= S.pcap && xcap <= S.xcap &&
+         (int64_t)g->ngroups + S.pcap <= g->gwl_cap;
+}
+
+namespace {
+
 // Every vertex affected, with its out-row counted as marked (nothing to
 // expand) and every group listed: the lock-free static and naive-dynamic
 // runs.
@@ -1807,6 +1967,11 @@ __global__ void k_mark_all(uint32_t *flags, int64_t fwords, uint32_t *gflags,
 template <typename T>
 int run_async(dfpr_graph *g, dfpr_stats *st, bool all = false) {
   hipStream_t s = g->stream;
+  {
+    int rc = ensure_split(g);
+    if (rc) return rc;
+  }
+  ++g->async_epoch;
   k_async_begin<<<1, 64, 0, s>>>(g->ctl);
   if (all) {
     // flag bytes past n in the last word and group bytes past the last
@@ -1817,9 +1982,15 @@ int run_async(dfpr_graph *g, dfpr_stats *st, bool all = false) {
     k_mark_all<<<grid_for(fwords, g->cu_count), 256, 0, s>>>(g->flags, fwords, g->gflags,
                                                              gwords);
   }
+  k_list_long<<<grid_for(g->n, g->cu_count), 256, 0, s>>>(
+      g->flags, g->in.deg, g->n, g->p.split_min_degree, g->ctl, g->split, g->gwl);
   k_list_groups<<<1, 256, 0, s>>>(g->gflags, g->ngroups, g->gwl, g->ctl);
   DFPR_HIP(hipGetLastError());
   RankArgs<T> A = make_args<T>(g, g->cur, g->cur);
+  // DF and DT updates stop by the lf_stop rule (make_args); the whole-set
+  // runs (lock-free static and naive-dynamic) always at the frontier
+  // tolerance
+  if (all) A.wtol = A.ftol;
   // grid from the groups listed by the marking (kChunksPerWave)
   DFPR_HIP(hipMemcpyAsync(g->h_ctl, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
   DFPR_HIP(hipStreamSynchronize(s));
@@ -1835,6 +2006,8 @@ int run_async(dfpr_graph *g, dfpr_stats *st, bool all = false) {
   k_df_async<T><<<blocks, g->p.block_size, lds, s>>>(A);
   DFPR_HIP(hipGetLastError());
   DFPR_HIP(hipEventRecord(g->ev[2], s));
+  k_zero_lcnt<<<grid_for(g->split.lcap, g->cu_count), 256, 0, s>>>(g->split.lcnt, g->ctl);
+  DFPR_HIP(hipGetLastError());
   DFPR_HIP(hipMemcpyAsync(g->h_ctl, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
   DFPR_HIP(hipStreamSynchronize(s));
   const Ctl h = *g->h_ctl;
@@ -2033,6 +2206,11 @@ int update_many_t(dfpr_graph *const *gs, int32_t count, dfpr_stats *stats) {
   for (dfpr_graph *g : act)
     if (g->stream != s) DFPR_HIP(hipStreamSynchronize(g->stream));
   const int na = (int)act.size();
+  for (dfpr_graph *g : act) {
+    int rc = ensure_split(g);
+    if (rc) return rc;
+    ++g->async_epoch;
+  }
   std::vector<RankArgs<T>> h(na);
   for (int i = 0; i < na; ++i) h[i] = make_args<T>(act[i], act[i]->cur, act[i]->cur);
   // device copies: descriptors, summaries, the done counter
@@ -2047,6 +2225,8 @@ int update_many_t(dfpr_graph *const *gs, int32_t count, dfpr_stats *stats) {
   DFPR_HIP(hipMemcpyAsync(d_desc, h.data(), dbytes, hipMemcpyHostToDevice, s));
   const int gb = grid_for(na, g0->cu_count);
   k_begin_many<T><<<gb, 256, 0, s>>>(d_desc, na, d_done);
+  k_list_long_many<T><<<na < g0->cu_count * 8 ? na : g0->cu_count * 8, 256, 0, s>>>(d_desc,
+                                                                                      na);
   k_list_groups_many<T><<<na < g0->cu_count * 8 ? na : g0->cu_count * 8, 256, 0, s>>>(d_desc,
                                                                                         na);
   k_gather_summary<T><<<gb, 256, 0, s>>>(d_desc, na, d_sum);

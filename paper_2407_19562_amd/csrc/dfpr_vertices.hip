@@ -146,7 +146,8 @@ int add_vertices(dfpr_graph *g, int32_t count, int32_t *first_id) {
   const size_t gb0 = flag_bytes(ng0);
   DFPR_HIP(hipMemsetAsync(reinterpret_cast<uint8_t *>(g->gflags) + ng0, 0, gb0 - ng0, s));
   if ((rc = grow_t(g, &g->gflags, gb0, flag_bytes(ng1), 0))) return rc;
-  if ((rc = grow_t(g, &g->gwl, ng0 * 4, ng1 * 4, 0xFF))) return rc;
+  if ((rc = grow_t(g, &g->gwl, g->gwl_cap * 4, (ng1 + g->split.pcap) * 4, 0xFF))) return rc;
+  g->gwl_cap = ng1 + g->split.pcap;
   if ((rc = grow_t(g, &g->wl, n0 * 4, n1 * 4, 0xFF))) return rc;
   if ((rc = grow_t(g, &g->steps, (n0 + 1) * 4, (n1 + 1) * 4, -1))) return rc;
   // tile sums are rebuilt by every update
@@ -162,6 +163,7 @@ int add_vertices(dfpr_graph *g, int32_t count, int32_t *first_id) {
   g->n = (int32_t)n1;
   g->ngroups = (int32_t)ng1;
   if ((rc = rescale_ranks(g, (int32_t)n0, (double)n0 / (double)n1))) return rc;
+  if ((rc = ensure_split(g))) return rc;
   DFPR_HIP(hipStreamSynchronize(s));
   if (first_id) *first_id = (int32_t)n0;
   return DFPR_OK;

@@ -29,6 +29,8 @@ DFPR_MEM_HOST = 0
 DFPR_MEM_DEVICE = 1
 DFPR_ASYNC = 0
 DFPR_SYNC = 1
+DFPR_STOP_TOL = 0
+DFPR_STOP_FRONTIER = 1
 DFPR_OUT = 0
 DFPR_IN = 1
 
@@ -55,7 +57,8 @@ class dfpr_params(ctypes.Structure):
                 ("split_min_degree", ctypes.c_int32), ("chunk", ctypes.c_int32),
                 ("block_size", ctypes.c_int32), ("reorder", ctypes.c_int32),
                 ("renormalize", ctypes.c_int32), ("timeout_ms", ctypes.c_int32),
-                ("grid_blocks", ctypes.c_int32), ("graph_replay", ctypes.c_int32)]
+                ("grid_blocks", ctypes.c_int32), ("graph_replay", ctypes.c_int32),
+                ("lf_stop", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -255,6 +255,13 @@ def rmat_small(seed: int = 1):
     return rmat(14, 8 << 14, seed)
 
 
+def rmat_mid(seed: int = 7):
+    """R-MAT with 2^20 vertices and average degree 4 (4,194,304 edges): the
+    smallest size at which the library switches to its large-graph paths
+    (1024-vertex tiles, degree-sorted vertex order)."""
+    return rmat(20, 4 << 20, seed)
+
+
 def rmat_large(seed: int = 2):
     """R-MAT with 2^22 vertices and 16*2^22 = 67,108,864 edges."""
     return rmat(22, 16 << 22, seed)
