@@ -306,6 +306,24 @@ int dfpr_update_traversal(dfpr_graph *g, dfpr_stats *stats);
  * stream is used).  stats[count] may be NULL.  Returns the worst status. */
 int dfpr_update_many(dfpr_graph *const *gs, int32_t count, dfpr_stats *stats);
 
+/* dfpr_update_many for callers that cannot allocate: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, results and returns as dfpr_update_many, but the launch's
+ * descriptors, summaries and done counter live in a fixed workspace that
+ * the library holds in each device's code object (about 1.5 MB per device,
+ * kept until the process ends), so the call makes no hipMalloc, hipFree or
+ * other allocating call on the host or the device.  At most
+ * DFPR_NOALLOC_MAX_GRAPHS graphs (DFPR_EINVAL above that).  Every graph's
+ * piece arrays must already fit its adjacency, which graph creation,
+ * dfpr_apply_batch, dfpr_set_params and dfpr_add_vertices guarantee
+ * (DFPR_ESTATE otherwise).  The workspace is shared by every call on a
+ * device and keeps the last call's contents; calls are serialised inside
+ * the library, and a caller that overlaps this call with dfpr_update_many
+ * on the same graphs races. */
+#define DFPR_NOALLOC_MAX_GRAPHS 4096
+int dfpr_update_many_noalloc(dfpr_graph *const *gs, int32_t count,
+                             dfpr_stats *stats);
+
 /* Copies the stored edges (self-loops excluded) of one direction to host
  * arrays src[cap], dst[cap] (row order unspecified); *count receives the
  * edge count.  DFPR_EINVAL if cap is too small. */

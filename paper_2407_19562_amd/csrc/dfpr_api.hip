@@ -19,6 +19,7 @@ int read_ranks_device(const dfpr_graph *g, double *out);
 int stream_copy(void *dst, const void *src, int64_t bytes, hipStream_t s,
                 float *ms);
 int update_many(dfpr_graph *const *gs, int32_t count, dfpr_stats *stats);
+int update_many_noalloc(dfpr_graph *const *gs, int32_t count, dfpr_stats *stats);
 
 static thread_local std::string g_last_error;
 
@@ -359,6 +360,13 @@ int dfpr_update_many(dfpr_graph *const *gs, int32_t count, dfpr_stats *stats) {
   for (int32_t i = 0; i < count; ++i)
     if (!gs[i]) return fail(DFPR_EINVAL, "NULL graph in list");
   return update_many(gs, count, stats);
+}
+
+int dfpr_update_many_noalloc(dfpr_graph *const *gs, int32_t count, dfpr_stats *stats) {
+  if (count < 0 || (count > 0 && !gs)) return fail(DFPR_EINVAL, "bad graph list");
+  for (int32_t i = 0; i < count; ++i)
+    if (!gs[i]) return fail(DFPR_EINVAL, "NULL graph in list");
+  return update_many_noalloc(gs, count, stats);
 }
 
 int dfpr_set_ranks(dfpr_graph *g, const double *r, int mem) {

@@ -35,6 +35,8 @@
 //                iterations.
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include <rocprim/device/device_scan.hpp>
@@ -2190,39 +2192,47 @@ int run_rank(dfpr_graph *g, int kind, dfpr_stats *st) {
 
 namespace {
 
+// Buffers of one batched launch: device memory for the descriptors, the
+// summaries and the done counter, and host staging for the same.  The
+// regular entry point grows them on demand; the allocation-free one passes
+// fixed arrays.
 template <typename T>
-int update_many_t(dfpr_graph *const *gs, int32_t count, dfpr_stats *stats) {
-  std::vector<dfpr_graph *> act;
+struct ManyWork {
+  void *dev = nullptr;  // device bytes >= count * (descriptor + summary) + 256
+  RankArgs<T> *hdesc = nullptr;
+  Summary *hsum = nullptr;
+  dfpr_graph **act = nullptr;
+};
+
+template <typename T>
+int update_many_t(dfpr_graph *const *gs, int32_t count, dfpr_stats *stats,
+                  const ManyWork<T> &W) {
+  dfpr_graph **act = W.act;
+  int na = 0;
   for (int32_t i = 0; i < count; ++i) {
     if (stats) {
       stats[i] = dfpr_stats{};
       stats[i].converged = 1;
     }
-    if (gs[i]->pending_marks > 0) act.push_back(gs[i]);
+    if (gs[i]->pending_marks > 0) act[na++] = gs[i];
   }
-  if (act.empty()) return DFPR_OK;
+  if (na == 0) return DFPR_OK;
   dfpr_graph *g0 = act[0];
   hipStream_t s = g0->stream;
-  for (dfpr_graph *g : act)
-    if (g->stream != s) DFPR_HIP(hipStreamSynchronize(g->stream));
-  const int na = (int)act.size();
-  for (dfpr_graph *g : act) {
-    int rc = ensure_split(g);
-    if (rc) return rc;
-    ++g->async_epoch;
-  }
-  std::vector<RankArgs<T>> h(na);
+  for (int i = 0; i < na; ++i)
+    if (act[i]->stream != s) DFPR_HIP(hipStreamSynchronize(act[i]->stream));
+  for (int i = 0; i < na; ++i) ++act[i]->async_epoch;
+  RankArgs<T> *h = W.hdesc;
   for (int i = 0; i < na; ++i) h[i] = make_args<T>(act[i], act[i]->cur, act[i]->cur);
-  // device copies: descriptors, summaries, the done counter
+  // device copies: descriptors, summaries, the done counter (set to 0 by
+  // k_begin_many, so nothing needs clearing beforehand)
   const size_t dbytes = sizeof(RankArgs<T>) * na;
   const size_t sbytes = sizeof(Summary) * na;
-  void *buf = nullptr;
-  int rc = scratch_get(g0, 12, dbytes + sbytes + 256, &buf);
-  if (rc) return rc;
+  void *buf = W.dev;
   RankArgs<T> *d_desc = (RankArgs<T> *)buf;
   Summary *d_sum = (Summary *)((char *)buf + dbytes);
   int *d_done = (int *)((char *)buf + dbytes + sbytes + 128);
-  DFPR_HIP(hipMemcpyAsync(d_desc, h.data(), dbytes, hipMemcpyHostToDevice, s));
+  DFPR_HIP(hipMemcpyAsync(d_desc, h, dbytes, hipMemcpyHostToDevice, s));
   const int gb = grid_for(na, g0->cu_count);
   k_begin_many<T><<<gb, 256, 0, s>>>(d_desc, na, d_done);
   k_list_long_many<T><<<na < g0->cu_count * 8 ? na : g0->cu_count * 8, 256, 0, s>>>(d_desc,
@@ -2230,8 +2240,8 @@ int update_many_t(dfpr_graph *const *gs, int32_t count, dfpr_stats *stats) {
   k_list_groups_many<T><<<na < g0->cu_count * 8 ? na : g0->cu_count * 8, 256, 0, s>>>(d_desc,
                                                                                         na);
   k_gather_summary<T><<<gb, 256, 0, s>>>(d_desc, na, d_sum);
-  std::vector<Summary> hs(na);
-  DFPR_HIP(hipMemcpyAsync(hs.data(), d_sum, sbytes, hipMemcpyDeviceToHost, s));
+  Summary *hs = W.hsum;
+  DFPR_HIP(hipMemcpyAsync(hs, d_sum, sbytes, hipMemcpyDeviceToHost, s));
   DFPR_HIP(hipStreamSynchronize(s));
   long long chunks = 0;
   for (int i = 0; i < na; ++i) chunks += claim_chunks(act[i], hs[i].gtail);
@@ -2252,7 +2262,7 @@ int update_many_t(dfpr_graph *const *gs, int32_t count, dfpr_stats *stats) {
   DFPR_HIP(hipGetLastError());
   DFPR_HIP(hipEventRecord(g0->ev[1], s));
   k_gather_summary<T><<<gb, 256, 0, s>>>(d_desc, na, d_sum);
-  DFPR_HIP(hipMemcpyAsync(hs.data(), d_sum, sbytes, hipMemcpyDeviceToHost, s));
+  DFPR_HIP(hipMemcpyAsync(hs, d_sum, sbytes, hipMemcpyDeviceToHost, s));
   k_cleanup_many<T><<<na < g0->cu_count * 8 ? na : g0->cu_count * 8, 256, 0, s>>>(d_desc, na);
   DFPR_HIP(hipGetLastError());
   DFPR_HIP(hipStreamSynchronize(s));
@@ -2298,8 +2308,9 @@ int update_many_t(dfpr_graph *const *gs, int32_t count, dfpr_stats *stats) {
 
 }  // namespace
 
-int update_many(dfpr_graph *const *gs, int32_t count, dfpr_stats *stats) {
-  if (count == 0) return DFPR_OK;
+namespace {
+
+int check_many(dfpr_graph *const *gs, int32_t count) {
   const int elem = gs[0]->elem;
   const int dev = gs[0]->device;
   for (int32_t i = 0; i < count; ++i) {
@@ -2308,10 +2319,120 @@ int update_many(dfpr_graph *const *gs, int32_t count, dfpr_stats *stats) {
     for (int32_t j = 0; j < i; ++j)
       if (gs[j] == gs[i]) return fail(DFPR_EINVAL, "a graph appears twice");
   }
-  int rc = elem == 8 ? update_many_t<double>(gs, count, stats)
-                     : update_many_t<float>(gs, count, stats);
-  if (rc >= 0 && elem == 4) {
+  return DFPR_OK;
+}
+
+int sync_fp32(dfpr_graph *const *gs, int32_t count, int rc) {
+  if (rc >= 0 && gs[0]->elem == 4) {
     for (int32_t i = 0; i < count; ++i) DFPR_HIP(hipStreamSynchronize(gs[i]->stream));
+  }
+  return rc;
+}
+
+}  // namespace
+
+int update_many(dfpr_graph *const *gs, int32_t count, dfpr_stats *stats) {
+  if (count == 0) return DFPR_OK;
+  int rc = check_many(gs, count);
+  if (rc) return rc;
+  for (int32_t i = 0; i < count; ++i)
+    if (gs[i]->pending_marks > 0 && (rc = ensure_split(gs[i]))) return rc;
+  std::vector<dfpr_graph *> act((size_t)count);
+  std::vector<Summary> hsum((size_t)count);
+  const size_t bytes = (sizeof(RankArgs<double>) + sizeof(Summary)) * (size_t)count + 256;
+  void *dev = nullptr;
+  if ((rc = scratch_get(gs[0], 12, bytes, &dev))) return rc;
+  if (gs[0]->elem == 8) {
+    std::vector<RankArgs<double>> hd((size_t)count);
+    rc = update_many_t<double>(gs, count, stats,
+                               ManyWork<double>{dev, hd.data(), hsum.data(), act.data()});
+  } else {
+    std::vector<RankArgs<float>> hd((size_t)count);
+    rc = update_many_t<float>(gs, count, stats,
+                              ManyWork<float>{dev, hd.data(), hsum.data(), act.data()});
+  }
+  return sync_fp32(gs, count, rc);
+}
+
+}  // namespace dfpr
+
+// --- the batched launch without allocation --------------------------------------
+//
+// Device workspace of dfpr_update_many_noalloc: a fixed array in the code
+// object, one copy per device, held until the process ends.  Host code
+// reaches it only through the address hipGetSymbolAddress returns for the
+// current device (the array's name is a host-side stand-in).
+namespace {
+constexpr int32_t kNoAllocMaxGraphs = DFPR_NOALLOC_MAX_GRAPHS;
+constexpr size_t kNoAllocBytes =
+    (sizeof(dfpr::RankArgs<double>) + sizeof(dfpr::Summary)) * kNoAllocMaxGraphs + 256;
+static_assert(sizeof(dfpr::RankArgs<double>) == sizeof(dfpr::RankArgs<float>),
+              "descriptors of both precisions share the workspace layout");
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace dfpr {
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;       // one allocation-free call at a time
+void *g_noalloc_dev[kMaxDevices];  // scratch's address per device
+// host staging, fixed size
+alignas(64) unsigned char g_noalloc_hdesc[sizeof(RankArgs<double>) * kNoAllocMaxGraphs];
+Summary g_noalloc_hsum[kNoAllocMaxGraphs];
+dfpr_graph *g_noalloc_act[kNoAllocMaxGraphs];
+
+// scratch's device address on `dev` (current), looked up once per device
+int noalloc_workspace(int dev, void **out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(DFPR_EINVAL, "device index out of range");
+  if (!g_noalloc_dev[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(DFPR_EHIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                 hipGetErrorString(e));
+    g_noalloc_dev[dev] = ptr;
+  }
+  *out = g_noalloc_dev[dev];
+  return DFPR_OK;
+}
+
+}  // namespace
+
+int update_many_noalloc(dfpr_graph *const *gs, int32_t count, dfpr_stats *stats) {
+  if (count > kNoAllocMaxGraphs)
+    return fail(DFPR_EINVAL, "dfpr_update_many_noalloc takes at most " +
+                                 std::to_string(kNoAllocMaxGraphs) + " graphs");
+  if (count == 0) return DFPR_OK;
+  int rc = check_many(gs, count);
+  if (rc) return rc;
+  for (int32_t i = 0; i < count; ++i)
+    if (gs[i]->pending_marks > 0 && !split_ready(gs[i]))
+      return fail(DFPR_ESTATE, "piece arrays of a graph are not sized for its adjacency");
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  const int dev = gs[0]->device;
+  int cur = -1;
+  DFPR_HIP(hipGetDevice(&cur));
+  if (cur != dev) DFPR_HIP(hipSetDevice(dev));
+  void *ws = nullptr;
+  rc = noalloc_workspace(dev, &ws);
+  if (rc == DFPR_OK) {
+    if (gs[0]->elem == 8)
+      rc = update_many_t<double>(
+          gs, count, stats,
+          ManyWork<double>{ws, reinterpret_cast<RankArgs<double> *>(g_noalloc_hdesc),
+                           g_noalloc_hsum, g_noalloc_act});
+    else
+      rc = update_many_t<float>(
+          gs, count, stats,
+          ManyWork<float>{ws, reinterpret_cast<RankArgs<float> *>(g_noalloc_hdesc),
+                          g_noalloc_hsum, g_noalloc_act});
+    rc = sync_fp32(gs, count, rc);
+  }
+  if (cur != dev) {
+    const hipError_t e = hipSetDevice(cur);
+    if (e != hipSuccess && rc >= 0) return fail(DFPR_EHIP, hipGetErrorString(e));
   }
   return rc;
 }

@@ -43,7 +43,8 @@ EXPORTS = (
     "dfpr_set_ranks", "dfpr_read_ranks",
     "dfpr_apply_batch", "dfpr_update", "dfpr_add_vertices",
     "dfpr_remove_vertices", "dfpr_mark_reachable",
-    "dfpr_update_traversal", "dfpr_update_many", "dfpr_read_edges",
+    "dfpr_update_traversal", "dfpr_update_many", "dfpr_update_many_noalloc",
+    "dfpr_read_edges",
     "dfpr_read_marks", "dfpr_graph_bytes", "dfpr_stream_copy",
     "dfpr_last_kernel_bytes", "dfpr_strerror", "dfpr_last_error",
 )
@@ -122,6 +123,7 @@ def _lib():
             "dfpr_remove_vertices": [V, i32],
             "dfpr_update_traversal": [V, P(dfpr_stats)],
             "dfpr_update_many": [V, i32, V],
+            "dfpr_update_many_noalloc": [V, i32, V],
             "dfpr_read_edges": [V, ctypes.c_int, V, V, i64, P(i64)],
             "dfpr_read_marks": [V, V, P(i64)],
             "dfpr_graph_bytes": [V, P(i64)],
@@ -289,6 +291,18 @@ def dfpr_update_many(graphs):
     rc = _check(_lib().dfpr_update_many(arr, len(graphs), stats),
                 "dfpr_update_many")
     return rc, list(stats)
+
+
+def dfpr_update_many_noalloc(graphs):
+    """dfpr_update_many without any allocation (fixed device workspace)."""
+    arr = (ctypes.c_void_p * len(graphs))(*[g.value if isinstance(g, ctypes.c_void_p) else g for g in graphs])
+    stats = (dfpr_stats * len(graphs))()
+    rc = _check(_lib().dfpr_update_many_noalloc(arr, len(graphs), stats),
+                "dfpr_update_many_noalloc")
+    return rc, list(stats)
+
+
+DFPR_NOALLOC_MAX_GRAPHS = 4096
 
 
 def dfpr_set_ranks(g, r) -> None:
