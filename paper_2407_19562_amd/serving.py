@@ -51,6 +51,9 @@ class Report:
     edges_gathered: int = 0
     batch_edges: int = 0
     admission_waits: int = 0
+    slot_waits: int = 0       # graphs with queued requests left waiting
+                              # because max_graphs were in flight
+    not_converged: int = 0    # updates that ended at the sweep cap
     apply_s: float = 0.0      # time spent applying batches (batched scheme)
     update_s: float = 0.0     # time spent in rank updates (each scheme:
                               # the whole run, applies and updates
@@ -67,6 +70,8 @@ class Report:
                 "edges_gathered_per_s": self.edges_gathered / max(self.wall_s, 1e-9),
                 "rounds": self.rounds, "updates": self.updates,
                 "admission_waits": self.admission_waits,
+                "slot_waits": self.slot_waits,
+                "not_converged": self.not_converged,
                 "apply_s": self.apply_s, "update_s": self.update_s,
                 "wall_s": self.wall_s}
 
@@ -118,6 +123,13 @@ class Server:
         self.coalesce = coalesce
         self.max_graphs = max_graphs
         self.reserve = reserve_bytes
+        # adjacency growth accounting for admission (per graph): insertions
+        # admitted since the last growth, the spare slots left for them, and
+        # the device bytes a growth of both adjacency arrays takes
+        m = [int(s.size) for _, s, _ in graphs]
+        self.inserted = [0] * len(m)
+        self.slack = [spare_slots(x) for x in m]
+        self.growth = [growth_bytes(x) for x in m]
 
     def close(self):
         if self.pool is not None:
@@ -132,23 +144,42 @@ class Server:
         except Exception:
             return 1 << 62
 
+    def _need(self, r):
+        """Device bytes request r may take: its staging (48 bytes per batch
+        edge: the batch arrays and both directions' sort keys) plus, when
+        its insertions may overflow the spare slots its graph has left, one
+        growth of both adjacency arrays.  Returns (bytes, grows)."""
+        need = 48 * r.batch.size
+        grows = self.inserted[r.graph] + int(r.batch.ins_src.size) > self.slack[r.graph]
+        if grows:
+            need += self.growth[r.graph]
+        return need, grows
+
     def _admit(self, rep, pending, queues, t0, open_loop, idle=False):
-        """Moves arrived requests whose staging fits in free memory to their
+        """Moves arrived requests whose device memory (staging and possible
+        adjacency growth) fits in free memory, above the reserve, to their
         graphs' queues.  idle: nothing is queued or in flight, so nothing
         will free memory; the first arrived request is admitted anyway."""
         now = time.perf_counter() - t0
         free = None
         while pending and (not open_loop or pending[0].arrival <= now):
             r = pending[0]
-            need = 48 * r.batch.size + self.reserve
+            need, grows = self._need(r)
             if free is None:
                 free = self._free_bytes()
-            if need > free and not idle:
+            if need + self.reserve > free and not idle:
                 rep.admission_waits += 1
                 break
             idle = False
-            free -= 48 * r.batch.size
-            queues[r.graph].append(pending.popleft())
+            free -= need
+            i = r.graph
+            if grows:
+                # the library grows an array to at least twice its slots
+                self.inserted[i] = 0
+                self.slack[i] *= 2
+                self.growth[i] *= 2
+            self.inserted[i] += int(r.batch.ins_src.size)
+            queues[i].append(pending.popleft())
 
     def _run_each(self, requests, open_loop: bool) -> Report:
         import concurrent.futures as cf
@@ -164,7 +195,9 @@ class Server:
             g = self.graphs[i]
             for r in take:
                 g.apply(r.batch)
-            st = g.update()[1]
+            rc, st = g.update()
+            if rc < 0:
+                raise RuntimeError(f"update of graph {i} failed ({rc})")
             return st, time.perf_counter() - t0
 
         while done < len(requests):
@@ -173,7 +206,9 @@ class Server:
             busy = {i for i, _ in inflight.values()}
             idle = [i for i, q in enumerate(queues) if q and i not in busy]
             idle.sort(key=lambda i: queues[i][0].arrival)
-            for i in idle[:max(0, limit - len(inflight))]:
+            free_slots = max(0, limit - len(inflight))
+            rep.slot_waits += max(0, len(idle) - free_slots)
+            for i in idle[:free_slots]:
                 take = [queues[i].popleft()
                         for _ in range(min(self.coalesce, len(queues[i])))]
                 rep.batch_edges += sum(r.batch.size for r in take)
@@ -195,6 +230,7 @@ class Server:
                 rep.rounds += 1           # one dispatch per graph update
                 rep.updates += 1
                 rep.edges_gathered += st.edges_gathered
+                rep.not_converged += 0 if st.converged else 1
                 for r in take:
                     r.done = end
                     rep.latencies_ms.append((end - r.arrival) * 1e3)
@@ -217,6 +253,7 @@ class Server:
             self._admit(rep, pending, queues, t0, open_loop, idle=not any(queues))
             active = [i for i, q in enumerate(queues) if q]
             if self.max_graphs and len(active) > self.max_graphs:
+                rep.slot_waits += len(active) - self.max_graphs
                 # the graphs whose oldest request waits longest go first
                 active.sort(key=lambda i: queues[i][0].arrival)
                 active = sorted(active[:self.max_graphs])
@@ -239,6 +276,9 @@ class Server:
                     self.graphs[i].apply(r.batch)
             tu = time.perf_counter()
             rc, stats = dfpr.dfpr_update_many([self.graphs[i].h for i in active])
+            if rc < 0:
+                raise RuntimeError(f"batched update failed ({rc})")
+            rep.not_converged += sum(0 if st.converged else 1 for st in stats)
             rep.apply_s += tu - ta
             rep.update_s += time.perf_counter() - tu
             end = time.perf_counter() - t0
@@ -252,6 +292,20 @@ class Server:
             done += len(served)
         rep.wall_s = time.perf_counter() - t0
         return rep
+
+
+def spare_slots(m: int) -> int:
+    """Insertions a graph of m edges takes before its adjacency may grow: the
+    spare tail is a quarter of the array (rows also keep a little slack of
+    their own, ignored here)."""
+    return max(1, m // 4)
+
+
+def growth_bytes(m: int) -> int:
+    """Device bytes one growth of both int32 adjacency arrays of a graph of
+    m edges takes: the new array (twice the slots, about 1.25 m each) next to
+    the old one until the copy is done."""
+    return 2 * 4 * 3 * (m + m // 4 + 64)
 
 
 def make_stream(graph_sizes, count: int, seed: int, rate: float | None,
@@ -290,9 +344,12 @@ def make_stream(graph_sizes, count: int, seed: int, rate: float | None,
     return reqs
 
 
-def bench(args, torch, dfpr_mod, inputs_mod, log):
+def bench(args, torch, dfpr_mod, inputs_mod, log, check=None):
     """Serving benchmark: resident R-MAT graphs, closed-loop saturated
-    throughput X, then open-loop Poisson streams at 0.5 X and 0.8 X."""
+    throughput X, then open-loop Poisson streams at 0.5 X and 0.8 X.
+    check(server, graphs, streams), if given, runs after the last stream
+    and before the graphs are freed (streams: the request lists in the order
+    they were served)."""
     count = args.graphs or 64
     nreq = args.requests or 20000
     t0 = time.time()
@@ -303,7 +360,9 @@ def bench(args, torch, dfpr_mod, inputs_mod, log):
     srv = Server(graphs, precision=32, scheme=args.scheme, max_graphs=args.max_graphs)
     try:
         res = {}
+        streams = []
         closed = make_stream(sizes, nreq, 4, None, edges_of=lambda g: graphs[g])
+        streams.append(closed)
         rep = srv.run(closed, open_loop=False)
         X = rep.summary()["throughput_batches_per_s"]
         res["closed_loop"] = rep.summary()
@@ -311,9 +370,11 @@ def bench(args, torch, dfpr_mod, inputs_mod, log):
         for frac in (0.5, 0.8):
             reqs = make_stream(sizes, nreq, 40 + int(frac * 10), frac * X,
                                edges_of=lambda g: graphs[g])
+            streams.append(reqs)
             rep = srv.run(reqs, open_loop=True)
             res[f"open_loop_{frac}X"] = rep.summary()
             log(f"open loop {frac}X: {res[f'open_loop_{frac}X']}")
+        checked = check(srv, graphs, streams) if check is not None else None
     finally:
         srv.close()
     o = res["open_loop_0.8X"]
@@ -328,4 +389,4 @@ def bench(args, torch, dfpr_mod, inputs_mod, log):
                        "ranks": "fp32 storage and sums, fp64 change tests and "
                        "renormalisation", "coalesce": srv.coalesce,
                        "scheme": srv.scheme, "max_graphs": srv.max_graphs},
-            "results": res}
+            "results": res, **({"error_vs_oracle": checked} if checked else {})}

@@ -21,20 +21,27 @@ def D():
 
 
 @pytest.mark.parametrize("scheme", ["batched", "each"])
-def test_served_equals_alone_and_oracle(D, scheme):
+@pytest.mark.parametrize("max_graphs", [8, 2])
+def test_served_equals_alone_and_oracle(D, scheme, max_graphs):
+    # max_graphs 2 < 6 graphs: requests wait for a slot while others are on
+    # the device
     import oracle
     from paper_2407_19562_amd import serving
-    print("serving mix", scheme, flush=True)
+    print("serving mix", scheme, max_graphs, flush=True)
     graphs = [inputs.rmat(11 + (i % 3), (8 + 4 * (i % 2)) << (11 + (i % 3)), seed=70 + i)
               for i in range(6)]
     sizes = [s.size for _, s, _ in graphs]
     reqs = serving.make_stream(sizes, 48, seed=11, rate=None, lo=1, hi=400,
                                edges_of=lambda g: graphs[g])
-    srv = serving.Server(graphs, precision=32, coalesce=3, scheme=scheme)
+    srv = serving.Server(graphs, precision=32, coalesce=3, scheme=scheme,
+                         max_graphs=max_graphs)
     try:
         rep = srv.run(reqs, open_loop=False)
         s = rep.summary()
         assert s["requests"] == 48 and s["p99_ms"] >= s["p50_ms"] > 0
+        assert s["not_converged"] == 0
+        if max_graphs < len(graphs):
+            assert s["slot_waits"] > 0
         # each update takes at most `coalesce` requests of one graph
         assert rep.updates >= 48 // 3 and rep.rounds >= 48 // (3 * 6)
         for gi, (n, src, dst) in enumerate(graphs):

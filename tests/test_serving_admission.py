@@ -9,10 +9,13 @@ import numpy as np
 from paper_2407_19562_amd import inputs, serving
 
 
-def _server(free):
+def _server(free, m=1 << 20):
     srv = serving.Server.__new__(serving.Server)   # no graphs, no device
     srv.reserve = 1 << 20
     srv._free_bytes = lambda: free
+    srv.inserted = [0]
+    srv.slack = [serving.spare_slots(m)]
+    srv.growth = [serving.growth_bytes(m)]
     return srv
 
 
@@ -46,3 +49,25 @@ def test_open_loop_respects_arrival_times():
     rep, queues = serving.Report(), [collections.deque()]
     srv._admit(rep, pending, queues, time.perf_counter(), open_loop=True)
     assert len(queues[0]) == 1 and len(pending) == 1
+
+
+def test_growth_counts_when_insertions_overflow_the_slack():
+    # a graph of 4096 edges has 1024 spare slots: the batch of 1000
+    # insertions fits, the next one would overflow and needs the growth
+    # bytes too
+    m = 4096
+    e = np.zeros(1000, np.int32)
+    big = inputs.Batch(np.zeros(0, np.int32), np.zeros(0, np.int32), e, e)
+    staging = 48 * 1000
+    free = (1 << 20) + 2 * staging + serving.growth_bytes(m) // 2
+    srv = _server(free=free, m=m)
+    pending = collections.deque([serving.Request(0, big, 0.0), serving.Request(0, big, 0.0)])
+    rep, queues = serving.Report(), [collections.deque()]
+    srv._admit(rep, pending, queues, time.perf_counter(), open_loop=False)
+    assert len(queues[0]) == 1 and len(pending) == 1 and rep.admission_waits == 1
+    assert srv.inserted[0] == 1000
+    # with room for the growth it is admitted, and the slack doubles
+    srv._free_bytes = lambda: (1 << 20) + staging + serving.growth_bytes(m)
+    srv._admit(rep, pending, queues, time.perf_counter(), open_loop=False)
+    assert len(queues[0]) == 2 and not pending
+    assert srv.slack[0] == 2 * serving.spare_slots(m) and srv.inserted[0] == 1000
