@@ -103,11 +103,15 @@ typedef struct {
                                added in piece order), the rest in
                                edge-balanced steps of up to 256 rows; in
                                the lock-free scheme a row's pieces are
-                               claimed like groups                         */
-  int32_t chunk;         /* lock-free scheme: vertices per claim, whole
-                            256-vertex groups (chunk / 256, at least one); a
-                            multiple of 64 in [64, 4096], or 0 (default):
-                            one group per 4096 groups of the graph, 1..16  */
+                               claimed like groups, and rows of 8192 or more
+                               in-edges always go in pieces there (a claim
+                               must stay short next to a sweep)            */
+  int32_t chunk;         /* lock-free scheme: vertices per wavefront of a
+                            claim, whole 256-vertex groups (chunk / 256, at
+                            least one); a multiple of 64 in [64, 4096], or
+                            0 (default): one group per 2048 groups of the
+                            graph, 1..8.  A claim is made by a whole
+                            workgroup, for all its wavefronts             */
   int32_t block_size;    /* threads per workgroup: 64, 128 (default), 192 or
                             256                                             */
   int32_t reorder;       /* internal vertex order, fixed at creation:

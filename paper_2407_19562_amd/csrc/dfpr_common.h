@@ -40,6 +40,19 @@ constexpr uint32_t kEX = 4u;  // all out-neighbours marked (synchronous DF)
 constexpr int kGroup = 256;
 constexpr int kGroupShift = 8;
 constexpr uint32_t kGA = 1u;  // group holds an affected vertex (listed)
+// Bits 4..6 of the group byte (set at the start of a lock-free launch):
+// log2 of the parts the group is claimed in.  A group whose rows below the
+// piece threshold hold many in-edges is split into up to 16 parts of equal
+// vertex ranges, so no claim holds a group far longer than the others
+// (with degree-sorted ids the first groups hold the heaviest rows).
+constexpr uint32_t kGPartShift = 4;
+constexpr int kMaxPartLog = 4;
+constexpr int32_t kPartEdges = 16384;  // target in-edges per part
+// Worklist entry of a group part: group | part << 23 | log2(parts) << 27
+// (non-negative); a piece of a long row is -(p + 2); -1 is an empty slot.
+constexpr int kEntryPartShift = 23;
+constexpr int32_t kEntryGroupMask = (1 << kEntryPartShift) - 1;
+constexpr int kEntryLogShift = 27;
 
 // Scheduling word of the persistent kernel (one 64-bit atomic):
 //   bit 63 done, bit 61 stopped at the sweep cap,
@@ -168,10 +181,9 @@ struct dfpr_graph {
   int32_t *wl = nullptr;
   int32_t ngroups = 0;
   uint32_t *gflags = nullptr;  // [ngroups] bytes
-  int32_t *gwl = nullptr;      // group worklist of the lock-free scheme, with
-                               // the pieces of its long rows
-                               // [gwl_cap >= ngroups + split.pcap], unused
-                               // slots -1
+  int32_t *gwl = nullptr;      // worklist of the lock-free scheme: group
+                               // parts and the pieces of long rows
+                               // [gwl_cap], unused slots -1
   int64_t gwl_cap = 0;
   int32_t async_epoch = 0;     // lock-free launches so far (piece tags)
   int32_t *steps = nullptr;    // step starts over the worklist [n + 1]

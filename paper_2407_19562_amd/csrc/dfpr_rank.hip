@@ -292,6 +292,28 @@ __device__ __forceinline__ void list_long_row(Ctl *ctl, int32_t *lrow, int32_t *
   for (int32_t k = 0; k < np; ++k) store_agent(gwl + pos + k, -(int32_t)(p0 + k) - 2);
 }
 
+// Lock-free scheme: appends the parts of newly listed groups (lanes with
+// `want`) to the worklist, with one atomic per wavefront.  All 64 lanes call
+// it.  The group byte carries log2(parts) (k_group_parts).
+__device__ __forceinline__ void append_group_parts(bool want, int32_t g,
+                                                   const uint32_t *gflags, int32_t *gwl,
+                                                   unsigned long long *gtail) {
+  if (__ballot(want) == 0) return;
+  uint32_t l = 0;
+  if (want) l = (flag_byte(gflags, g, true) >> kGPartShift) & 7u;
+  const int32_t cnt = want ? (1 << l) : 0;
+  const int32_t incl = wave_incl_scan(cnt);
+  const int32_t total = __shfl(incl, kWave - 1);
+  unsigned long long base = 0;
+  if (lane_id() == 0)
+    base = __hip_atomic_fetch_add(gtail, (unsigned long long)total, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+  base = __shfl(base, 0);
+  for (int32_t p = 0; p < cnt; ++p)
+    store_agent(gwl + base + (incl - cnt) + p,
+                g | (p << kEntryPartShift) | ((int32_t)l << kEntryLogShift));
+}
+
 // Synchronous scheme: marks w affected; true when w is newly affected.
 __device__ __forceinline__ bool mark_vertex_sync(uint32_t *flags, int32_t w) {
   if (flag_byte(flags, w, false) & kVA) return false;
@@ -328,7 +350,7 @@ __device__ __forceinline__ void expand_flat(const RankArgs<T> &A, WaveLds<T> &L,
         MarkOut o{false, false, -1};
         if (w[j] >= 0) o = mark_affected(A.flags, A.gflags, w[j]);
         newly += o.vnew ? 1 : 0;
-        wave_append(o.gnew, o.g, A.gwl, &A.ctl->gtail, true);
+        append_group_parts(o.gnew, o.g, A.gflags, A.gwl, &A.ctl->gtail);
         if (o.vnew) {
           // a long row joins the worklist as pieces (its group skips it)
           const int32_t dw = A.in_deg[w[j]];
@@ -564,15 +586,16 @@ __device__ __forceinline__ void flush_counters(Ctl *ctl, Counters &c) {
 //
 // Convergence (Algorithm 2's R_C flags, kept per claim): a claim that saw
 // a rank change above the watermark tolerance wtol (the iteration
-// tolerance for DF updates), affected a new vertex, or met an entry it
+// tolerance for DF updates, or the frontier tolerance) or met an entry it
 // could not finish raises change_sweep to the sweep index current when it
-// completes (a returning atomic after a release fence, performed before
-// the claim drops its in-flight mark).  Sweep S may end the launch only
-// when no claim is held and change_sweep < S: then every worklist entry was
-// processed during S, no rank moved by more than wtol and no vertex became
-// affected, so every R_C is 0 and every affected vertex has been
-// recomputed.  Otherwise the next sweep starts at once, without waiting for
-// claims still held (no barrier).
+// is published (after a release fence, and before the claim's in-flight
+// mark drops).  Sweep S may end the launch only when no claim is held and
+// change_sweep < S: then every worklist entry was processed during S and
+// no rank moved by more than wtol, so every R_C is 0.  Otherwise the next
+// sweep starts as soon as a claim completed during S has seen a change,
+// without waiting for the other claims still held (no barrier).  (Starting
+// it before any such change was tried: no faster, and one clean sweep more
+// at the end.)
 template <typename T>
 __device__ void sweep_end(const RankArgs<T> &A, unsigned long long W,
                           int *done_count) {
@@ -585,6 +608,8 @@ __device__ void sweep_end(const RankArgs<T> &A, unsigned long long W,
   const long long cs = load_agent(&A.ctl->change_sweep);
   unsigned long long nw;
   if (cs >= (long long)sweep) {
+    // a claim completed during this sweep saw a change: the next sweep
+    // starts at once, while this sweep's other claims finish
     const unsigned long long ns = sweep + 1;
     if ((long long)ns >= A.max_iters)
       nw = kDone | kCapped | (ns << kSweepShift);
@@ -596,7 +621,7 @@ __device__ void sweep_end(const RankArgs<T> &A, unsigned long long W,
     if (load_agent(&A.ctl->change_sweep) >= (long long)sweep) return;
     nw = kDone | ((sweep + 1) << kSweepShift);
   } else {
-    return;
+    return;  // claims in flight, no change seen in this sweep yet: wait
   }
   unsigned long long expect = W;
   const bool won = __hip_atomic_compare_exchange_strong(
@@ -604,94 +629,191 @@ __device__ void sweep_end(const RankArgs<T> &A, unsigned long long W,
   if (won && (nw & kDone) && done_count) atomicAdd(done_count, 1);
 }
 
-enum StepResult { kWorked = 0, kNoWork = 1, kGraphDone = 2 };
+enum StepResult { kWorked = 0, kNoWork = 1, kGraphDone = 2, kStop = 3 };
 
-// One scheduling step of the lock-free scheme on one graph: claim
-// `per` positions of its group worklist and process them in place (the
-// affected vertices of a group, or a piece of an affected long row).  A graph never gets more claim holders than it
-// has listed groups; beyond that, extra wavefronts would only start new
-// sweeps over groups still being processed.
+// Scheduling state of one workgroup of the lock-free scheme on one graph
+// (the same copy in every thread; `seen` is kept by thread 0).
+//
+// Claims are made per workgroup, and the workgroup's wavefronts share the
+// claimed entries: the scheduling word is one per graph, and every
+// operation on it is a round trip to the device's coherence point, so
+// wavefronts claiming one by one either waited on the word (many small
+// claims) or were too few to keep the memory system busy (few large ones).
+// A workgroup keeps its in-flight mark after a claim and trades it for the
+// next claim in the same fetch_add (the cursor advances, the count stays).
+// The change of the finished claim is published after that atomic, while
+// the new mark still keeps the sweep from ending, and only when the
+// watermark the workgroup last saw is below the current sweep.
+struct WaveSched {
+  bool held = false;       // holds an in-flight mark
+  bool moved = false;      // its finished claim saw a change to publish
+  long long seen = -1;     // change_sweep as last returned (thread 0)
+  unsigned idle = 0;       // consecutive steps without work (backoff)
+  unsigned polls = 0;      // steps made (abort polling)
+};
+
+// Thread 0's decision of a step, broadcast to the workgroup.
+struct ClaimShare {
+  unsigned long long p, end;
+  int code;
+  int held;
+};
+
+// Thread 0: publishes a finished claim's change at sweep `now`.
+template <typename T>
+__device__ __forceinline__ void publish(const RankArgs<T> &A, WaveSched &ws, long long now) {
+  if (ws.seen < now) {
+    const long long before = __hip_atomic_fetch_max(&A.ctl->change_sweep, now, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+    ws.seen = before > now ? before : now;
+  }
+}
+
+// Thread 0: drops the workgroup's in-flight mark, publishing its last
+// change first (the workgroup's stores are already performed).
+template <typename T>
+__device__ __forceinline__ void release_mark(const RankArgs<T> &A, WaveSched &ws) {
+  if (!ws.held) return;
+  if (ws.moved)
+    publish(A, ws, (long long)((load_agent(&A.ctl->state) >> kSweepShift) & kSweepMask));
+  // the watermark update is performed before the in-flight mark drops
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __hip_atomic_fetch_sub(&A.ctl->state, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  ws.held = false;
+  ws.moved = false;
+}
+
+// Processes one worklist entry in place: the affected vertices of a group
+// part, or a piece of an affected long row.  One wavefront.
+template <typename T>
+__device__ __forceinline__ void process_entry(const RankArgs<T> &A, WaveLds<T> &L,
+                                              unsigned long long gp, Counters &cnt,
+                                              long long &newly, bool &moved) {
+  const int lane = lane_id();
+  double unused = 0.0;
+  int32_t x = -1;
+  if (lane == 0) x = load_agent(A.gwl + gp);
+  x = __builtin_amdgcn_readfirstlane(x);
+  if (x == -1) {
+    // slot reserved, entry not yet stored: its appender still holds a
+    // mark; count it as work left all the same
+    moved = true;
+    return;
+  }
+  if (x <= -2) {  // a piece of an affected long row
+    process_piece<T, kAsync>(A, L, -x - 2, cnt, unused, newly, moved);
+    return;
+  }
+  // a part of a group: its vertex range of 256 >> l ids
+  const int32_t l = (x >> kEntryLogShift) & 7;
+  const int32_t span = kGroup >> l;
+  const int32_t v0 = ((x & kEntryGroupMask) << kGroupShift) +
+                     ((x >> kEntryPartShift) & 15) * span;
+  int32_t vv[kQ];
+#pragma unroll
+  for (int k = 0; k < kQ; ++k) {
+    const int32_t o = k * kWave + lane;
+    const int32_t v = v0 + o;
+    vv[k] = (o < span && v < A.n && (flag_byte(A.flags, v, true) & kVA)) ? v : -1;
+  }
+  process_step<T, kAsync>(A, L, vv, cnt, unused, newly, moved);
+}
+
+// Idle backoff: 64 * 2^min(idle, 4) sleep units, so workgroups without work
+// poll the scheduling word less often the longer they find nothing.
+__device__ __forceinline__ void idle_sleep(unsigned idle) {
+  const unsigned k = idle < 4 ? idle : 4;
+  for (unsigned i = 0; i < (1u << k); ++i) __builtin_amdgcn_s_sleep(64);
+}
+
+// One scheduling step of the lock-free scheme on one graph, made by the
+// whole workgroup: thread 0 claims `per` positions of the worklist (a
+// workgroup without a mark first reads the word, so that idle workgroups
+// neither claim past the end nor hold more marks than the graph has
+// entries), and the wavefronts process the claimed entries in turn.  Thread
+// 0 also polls the abort flag and the watchdog; kStop ends the kernel.
 template <typename T>
 __device__ int df_async_step(const RankArgs<T> &A, WaveLds<T> &L, Counters &cnt,
-                             long long &newly, unsigned long long per,
-                             int *done_count) {
-  const int lane = lane_id();
-  const unsigned long long grab = (per << kCursorShift) | 1ull;
-  unsigned long long W = 0, gt = 0;
-  if (lane == 0) {
-    W = load_agent(&A.ctl->state);
-    gt = load_agent(&A.ctl->gtail);
+                             long long &newly, unsigned long long per, int *done_count,
+                             int *abort_flag, unsigned long long t_start,
+                             unsigned long long timeout_ticks, WaveSched &ws,
+                             ClaimShare &sh) {
+  if (threadIdx.x == 0) {
+    int code = kWorked;
+    unsigned long long p = 0, end = 0;
+    ++ws.polls;
+    if ((ws.polls & 15u) == 0 && load_agent(abort_flag)) {
+      code = kStop;
+    } else if (ws.idle > 0 && timeout_ticks && (ws.polls & 63u) == 0 &&
+               wall_clock64() - t_start > timeout_ticks) {
+      store_agent(abort_flag, 1);
+      code = kStop;
+    } else if (!ws.held) {
+      const unsigned long long W = load_agent(&A.ctl->state);
+      const unsigned long long gt = load_agent(&A.ctl->gtail);
+      if (W & kDone) {
+        code = kGraphDone;
+      } else if (((W >> kCursorShift) & kCursorMask) >= gt) {
+        sweep_end(A, W, done_count);
+        code = kNoWork;
+      } else if ((W & kInflightMask) >= gt) {
+        code = kNoWork;
+      }
+    }
+    if (code == kWorked) {
+      // claim: cursor += per for each wavefront, and one more mark unless
+      // the workgroup holds one
+      const unsigned long long take = per * (blockDim.x / kWave);
+      const unsigned long long grab = (take << kCursorShift) | (ws.held ? 0ull : 1ull);
+      const unsigned long long W2 = __hip_atomic_fetch_add(&A.ctl->state, grab, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned long long gt = load_agent(&A.ctl->gtail);
+      // the previous claim's change, at the sweep current now: changes made
+      // late in an old sweep still force a fresh full sweep
+      if (ws.moved) publish(A, ws, (long long)((W2 >> kSweepShift) & kSweepMask));
+      ws.moved = false;
+      ws.held = true;
+      if (W2 & kDone) {
+        // the sweep cap ended the update: nothing more to give back
+        ws.held = false;
+        code = kGraphDone;
+      } else {
+        p = (W2 >> kCursorShift) & kCursorMask;
+        if (p >= gt) {
+          release_mark(A, ws);
+          // the cursor has passed the end: try to close the sweep
+          sweep_end(A, load_agent(&A.ctl->state), done_count);
+          code = kNoWork;
+        } else {
+          end = p + take < gt ? p + take : gt;
+        }
+      }
+    }
+    sh.p = p;
+    sh.end = end;
+    sh.code = code;
+    sh.held = ws.held ? 1 : 0;
   }
-  W = bcast0(W);
-  gt = bcast0(gt);
-  if (W & kDone) return kGraphDone;
-  if (((W >> kCursorShift) & kCursorMask) >= gt) {
-    if (lane == 0) sweep_end(A, W, done_count);
-    return kNoWork;
+  __syncthreads();
+  const int code = sh.code;
+  const unsigned long long p = sh.p, end = sh.end;
+  ws.held = sh.held != 0;
+  if (code != kWorked) {
+    ws.moved = false;
+    ++ws.idle;
+    __syncthreads();  // sh is read before thread 0 writes it again
+    return code;
   }
-  if ((W & kInflightMask) >= gt) return kNoWork;
-  unsigned long long W2 = 0;
-  if (lane == 0) {
-    W2 = __hip_atomic_fetch_add(&A.ctl->state, grab, __ATOMIC_RELAXED,
-                                __HIP_MEMORY_SCOPE_AGENT);
-    gt = load_agent(&A.ctl->gtail);
-  }
-  W2 = bcast0(W2);
-  gt = bcast0(gt);
-  if (W2 & kDone) return kGraphDone;
-  const unsigned long long p = (W2 >> kCursorShift) & kCursorMask;
-  if (p >= gt) {
-    if (lane == 0)
-      __hip_atomic_fetch_sub(&A.ctl->state, 1ull, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-    return kNoWork;
-  }
-  const unsigned long long end = p + per < gt ? p + per : gt;
+  ws.idle = 0;
+  const unsigned w = threadIdx.x / kWave, nw = blockDim.x / kWave;
   bool moved = false;
-  double unused = 0.0;
-  for (unsigned long long gp = p; gp < end; ++gp) {
-    int32_t x = -1;
-    if (lane == 0) x = load_agent(A.gwl + gp);
-    x = __builtin_amdgcn_readfirstlane(x);
-    if (x == -1) {
-      // slot reserved, entry not yet stored: its appender's claim raises
-      // the watermark; count it as work left all the same
-      moved = true;
-      continue;
-    }
-    if (x <= -2) {  // a piece of an affected long row
-      process_piece<T, kAsync>(A, L, -x - 2, cnt, unused, newly, moved);
-      continue;
-    }
-    const int32_t v0 = x << kGroupShift;
-    int32_t vv[kQ];
-#pragma unroll
-    for (int k = 0; k < kQ; ++k) {
-      const int32_t v = v0 + k * kWave + lane;
-      vv[k] = (v < A.n && (flag_byte(A.flags, v, true) & kVA)) ? v : -1;
-    }
-    process_step<T, kAsync>(A, L, vv, cnt, unused, newly, moved);
-  }
-  const bool any = __ballot(moved) != 0;
-  if (lane == 0) {
-    // every store of this claim (ranks, contributions, flags, worklist
-    // entries) is performed before the watermark and the in-flight count
-    // change: a sweep that ends the launch sees them
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    long long seen = 0;
-    if (any) {
-      // the sweep current now (not the claim's): changes made late in an
-      // old sweep still force a fresh full sweep
-      const long long now =
-          (long long)((load_agent(&A.ctl->state) >> kSweepShift) & kSweepMask);
-      seen = __hip_atomic_fetch_max(&A.ctl->change_sweep, now, __ATOMIC_RELAXED,
-                                    __HIP_MEMORY_SCOPE_AGENT);
-    }
-    // the watermark update must be performed before the in-flight mark drops
-    asm volatile("" ::"v"(seen) : "memory");
-    __hip_atomic_fetch_sub(&A.ctl->state, 1ull, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-  }
+  for (unsigned long long gp = p + w; gp < end; gp += nw)
+    process_entry<T>(A, L, gp, cnt, newly, moved);
+  // every store of this claim (ranks, contributions, flags, worklist
+  // entries), by every wavefront, is performed before the workgroup's next
+  // operation on the scheduling word, which gives its mark back
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  ws.moved = __syncthreads_or(moved ? 1 : 0) != 0;
   return kWorked;
 }
 
@@ -714,33 +836,34 @@ __device__ __forceinline__ unsigned long long groups_per_claim(int chunk) {
 // The lock-free persistent kernel for one graph.
 template <typename T>
 __global__ void __launch_bounds__(256) k_df_async(RankArgs<T> A) {
+  __shared__ ClaimShare sh;
   WaveLds<T> &L = wave_lds<T>();
-  const int lane = lane_id();
   Counters cnt;
   long long newly = 0;
   const unsigned long long t_start = wall_clock64();
   const unsigned long long per = groups_per_claim(A.chunk);
-  unsigned polls = 0;
+  WaveSched ws;
   while (true) {
-    int ab = 0;
-    if (lane == 0 && (++polls & 15u) == 0) ab = load_agent(&A.ctl->abort);
-    if (__builtin_amdgcn_readfirstlane(ab)) break;
-    const int r = df_async_step<T>(A, L, cnt, newly, per, nullptr);
-    if (r == kGraphDone) break;
-    if (r == kWorked && injected_fault(A)) break;  // holds no claim here
-    if (r == kNoWork) {
-      __builtin_amdgcn_s_sleep(32);
-      if (A.timeout_ticks && ((polls & 63u) == 0) &&
-          wall_clock64() - t_start > A.timeout_ticks) {
-        if (lane == 0) store_agent(&A.ctl->abort, 1);
+    const int r = df_async_step<T>(A, L, cnt, newly, per, nullptr, &A.ctl->abort, t_start,
+                                   A.timeout_ticks, ws, sh);
+    if (r == kGraphDone || r == kStop) break;
+    if (r == kWorked) {
+      if (injected_fault(A)) {
+        // a stop at a claim boundary: the mark goes back first, so the
+        // others can finish the update
+        if (threadIdx.x == 0) release_mark(A, ws);
         break;
       }
+      continue;
     }
+    idle_sleep(ws.idle - 1);
   }
   flush_graph<T>(A.ctl, cnt, newly);
 }
 
-// The lock-free persistent kernel for many graphs at once: each wavefront
+constexpr int kManyBits = 4096;
+
+// The lock-free persistent kernel for many graphs at once: each workgroup
 // works on one graph until it finds nothing to claim there, then moves to
 // the next; the launch ends when every graph's update has ended.
 template <typename T>
@@ -748,43 +871,61 @@ __global__ void __launch_bounds__(256) k_df_async_many(const RankArgs<T> *descs,
                                                        int count, int *done_count,
                                                        int *abort_flag,
                                                        unsigned long long timeout_ticks) {
+  __shared__ ClaimShare sh;
+  __shared__ int all_done;
+  // graphs this workgroup has seen finished (the first kManyBits of them):
+  // skipped without touching their scheduling words
+  __shared__ uint32_t seen_done[kManyBits / 32];
+  for (int i = threadIdx.x; i < kManyBits / 32; i += blockDim.x) seen_done[i] = 0u;
   WaveLds<T> &L = wave_lds<T>();
-  const int lane = lane_id();
-  const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  int gi = (int)(wave % count);
+  int gi = (int)(blockIdx.x % (unsigned)count);
   RankArgs<T> A = descs[gi];
   unsigned long long per = groups_per_claim(A.chunk);
   Counters cnt;
   long long newly = 0;
   const unsigned long long t_start = wall_clock64();
   int idle = 0;
-  unsigned polls = 0;
+  unsigned laps = 0;
+  WaveSched ws;
   while (true) {
-    int dc = 0, ab = 0;
-    if (lane == 0) {
-      dc = load_agent(done_count);
-      if ((++polls & 15u) == 0) ab = load_agent(abort_flag);
-    }
-    dc = __builtin_amdgcn_readfirstlane(dc);
-    ab = __builtin_amdgcn_readfirstlane(ab);
-    if (dc >= count || ab) break;
-    const int r = df_async_step<T>(A, L, cnt, newly, per, done_count);
+    if (threadIdx.x == 0) all_done = load_agent(done_count) >= count;
+    __syncthreads();
+    const bool stop_all = all_done != 0;
+    __syncthreads();
+    if (stop_all) break;
+    const int r = df_async_step<T>(A, L, cnt, newly, per, done_count, abort_flag, t_start,
+                                   timeout_ticks, ws, sh);
+    if (r == kStop) break;
     if (r == kWorked) {
       idle = 0;
+      laps = 0;
       continue;
     }
-    // nothing to claim here: move on (a full lap without work backs off)
+    // nothing to claim here (no mark held): move on to the next graph not
+    // seen finished
     flush_graph<T>(A.ctl, cnt, newly);
-    gi = gi + 1 < count ? gi + 1 : 0;
-    A = descs[gi];
-    per = groups_per_claim(A.chunk);
-    if (++idle >= count) {
-      idle = 0;
-      __builtin_amdgcn_s_sleep(32);
-      if (timeout_ticks && wall_clock64() - t_start > timeout_ticks) {
-        if (lane == 0) store_agent(abort_flag, 1);
+    if (r == kGraphDone && gi < kManyBits && threadIdx.x == 0)
+      seen_done[gi >> 5] |= 1u << (gi & 31);
+    __syncthreads();
+    int next = gi;
+    for (int k = 1; k <= count; ++k) {
+      const int c = gi + k < count ? gi + k : gi + k - count;
+      if (c >= kManyBits || !(seen_done[c >> 5] & (1u << (c & 31)))) {
+        next = c;
         break;
       }
+    }
+    __syncthreads();
+    gi = next;
+    A = descs[gi];
+    per = groups_per_claim(A.chunk);
+    const unsigned polls = ws.polls;
+    ws = WaveSched();  // the watermark seen belongs to the previous graph
+    ws.polls = polls;
+    // eight visits without work (or a lap over fewer graphs) back off
+    if (++idle >= (count < 8 ? count : 8)) {
+      idle = 0;
+      idle_sleep(laps++);
     }
   }
   flush_graph<T>(A.ctl, cnt, newly);
@@ -1012,16 +1153,18 @@ __global__ void k_cleanup(uint32_t *flags, int32_t *wl,
 }
 
 // Clears the group flags, the vertex flags of every listed group and the
-// group worklist (one thread per listed group).
+// group worklist (one thread per worklist entry; the parts of a group clear
+// the same flags, pieces nothing).
 __global__ void k_cleanup_groups(uint32_t *gflags, uint32_t *flags, int32_t *gwl,
                                  unsigned long long glen, int32_t n) {
   const int64_t words_per_group = kGroup / 4;
   const int64_t wmax = ((int64_t)n + 3) / 4;
   for (unsigned long long i = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x;
        i < glen; i += (unsigned long long)gridDim.x * blockDim.x) {
-    const int32_t grp = gwl[i];
+    const int32_t x = gwl[i];
     gwl[i] = -1;
-    if (grp < 0) continue;
+    if (x < 0) continue;
+    const int32_t grp = x & kEntryGroupMask;
     const int64_t w0 = (int64_t)grp * words_per_group;
     for (int64_t k = 0; k < words_per_group && w0 + k < wmax; ++k) flags[w0 + k] = 0u;
     reinterpret_cast<uint8_t *>(gflags)[grp] = 0;
@@ -1085,9 +1228,10 @@ __global__ void k_cleanup_many(const RankArgs<T> *descs, int count) {
     }
     const int64_t wmax = ((int64_t)A.n + 3) / 4;
     for (unsigned long long k = threadIdx.x; k < glen; k += blockDim.x) {
-      const int32_t grp = A.gwl[k];
+      const int32_t x = A.gwl[k];
       A.gwl[k] = -1;
-      if (grp < 0) continue;
+      if (x < 0) continue;
+      const int32_t grp = x & kEntryGroupMask;
       const int64_t w0 = (int64_t)grp * (kGroup / 4);
       for (int64_t q = 0; q < kGroup / 4 && w0 + q < wmax; ++q) A.flags[w0 + q] = 0u;
       reinterpret_cast<uint8_t *>(A.gflags)[grp] = 0;
@@ -1225,21 +1369,26 @@ inline int grid_for(int64_t work, int cu) {
   return (int)(b < 1 ? 1 : b);
 }
 
-// Lock-free scheme: vertices per claim (whole 256-vertex groups).  chunk 0
-// picks one group per 4096 groups of the graph, between 1 and 16: on the
-// 2^22 R-MAT (16384 groups) four groups per claim ran 2.5x faster than one.
+// Lock-free scheme: vertices per wavefront of a claim (whole 256-vertex
+// groups; a workgroup claims that many for each of its wavefronts).  chunk
+// 0 picks one group per 2048 groups of the graph, between 1 and 8: on the
+// 2^22 R-MAT (16384 groups) claims of 16 groups for a two-wavefront
+// workgroup ran 1.6x faster than claims of 4 by single wavefronts, which
+// had run 2.5x faster than claims of one (every claim is an atomic on the
+// one scheduling word, and idle workgroups poll it).
 inline int effective_chunk(const dfpr_graph *g) {
   if (g->p.chunk > 0) return g->p.chunk;
-  int per = g->ngroups / 4096;
-  per = per < 1 ? 1 : (per > 16 ? 16 : per);
+  int per = g->ngroups / 2048;
+  per = per < 1 ? 1 : (per > 8 ? 8 : per);
   return per * kGroup;
 }
 
-// Lock-free grid: enough wavefronts that each takes about kChunksPerWave
-// claims per sweep.  With more claim holders than a sweep has chunks, new
-// sweeps start over groups still being processed and every wavefront
-// contends for the one scheduling word (the 2^22 R-MAT ran 8x slower with
-// every co-resident wavefront than with a quarter of them).
+// Lock-free grid: enough workgroups that each takes about kChunksPerWave
+// claims per sweep (a claim is one workgroup's, shared by its wavefronts).
+// With more claim holders than a sweep has chunks, new sweeps start over
+// entries still being processed and every workgroup contends for the one
+// scheduling word (the 2^22 R-MAT ran 8x slower with every co-resident
+// wavefront claiming than with a quarter of them).
 constexpr int kChunksPerWave = 4;
 
 inline long long claim_chunks(const dfpr_graph *g, unsigned long long gtail) {
@@ -1247,15 +1396,18 @@ inline long long claim_chunks(const dfpr_graph *g, unsigned long long gtail) {
   return ((long long)gtail + per - 1) / per;
 }
 
-// Wavefronts for `chunks` claimable chunks per sweep: one per chunk up to
-// four per CU (small graphs: the 2^14 R-MAT's 64 groups ran 3.7x faster with 64
-// wavefronts than with 16), beyond that one per kChunksPerWave chunks.
-inline long long async_waves(long long chunks, int cu_count) {
-  const long long floor_w = 4ll * (cu_count > 0 ? cu_count : 1);
-  long long w = (chunks + kChunksPerWave - 1) / kChunksPerWave;
-  if (w < floor_w) w = floor_w;
-  if (w > chunks) w = chunks;
-  return w > 0 ? w : 1;
+// Workgroups for `chunks` wavefront chunks per sweep (a workgroup claims
+// one per wavefront): one claim per workgroup up to four wavefronts per CU
+// in all (small graphs: the 2^14 R-MAT's 64 groups ran 3.7x faster with 64
+// wavefronts than with 16), beyond that one per kChunksPerWave claims.
+inline long long async_blocks(long long chunks, int cu_count, int waves_per_block) {
+  const long long claims = (chunks + waves_per_block - 1) / waves_per_block;
+  const long long floor_b =
+      (4ll * (cu_count > 0 ? cu_count : 1) + waves_per_block - 1) / waves_per_block;
+  long long b = (claims + kChunksPerWave - 1) / kChunksPerWave;
+  if (b < floor_b) b = floor_b;
+  if (b > claims) b = claims;
+  return b > 0 ? b : 1;
 }
 
 template <typename T>
@@ -1542,22 +1694,69 @@ __global__ void __launch_bounds__(256) k_tile_emit(const uint32_t *flags,
 
 // Group worklist of the lock-free scheme from the listed flags: one
 // 256-thread workgroup per graph compacts the graph's group flags in id
-// order into gwl after the entries already there (the pieces of the long
-// rows, k_list_long) and sets gtail.
+// order into gwl, each listed group as its parts (log2 in the group byte),
+// after the entries already there (the pieces of the long rows,
+// k_list_long), and sets gtail.
 __device__ __forceinline__ void list_groups(const uint8_t *gflags, int32_t ngroups,
                                             int32_t *gwl, unsigned long long *gtail) {
   __shared__ int32_t lds4[4];
   int32_t base = (int32_t)*gtail;
   for (int32_t g0 = 0; g0 < ngroups; g0 += kRows) {
     const int32_t gi = g0 + (int32_t)threadIdx.x;
-    const bool sel = gi < ngroups && (gflags[gi] & kGA);
+    const uint32_t b = gi < ngroups ? gflags[gi] : 0u;
+    const bool sel = (b & kGA) != 0;
+    const int32_t l = (int32_t)((b >> kGPartShift) & 7u);
+    const int32_t cnt = sel ? (1 << l) : 0;
     int32_t total = 0;
-    const int32_t pos = block_excl_scan(sel ? 1 : 0, lds4, &total);
-    if (sel) gwl[base + pos] = gi;
+    const int32_t pos = block_excl_scan(cnt, lds4, &total);
+    for (int32_t p = 0; p < cnt; ++p)
+      gwl[base + pos + p] = gi | (p << kEntryPartShift) | (l << kEntryLogShift);
     base += total;
   }
   __syncthreads();  // every thread has read *gtail
   if (threadIdx.x == 0) *gtail = (unsigned long long)base;
+}
+
+// Lock-free scheme, at launch: the parts of every group (listed or not:
+// groups listed later read them too), from the in-edges of its rows below
+// the piece threshold.  One wavefront per group; the group byte keeps its
+// other bits.
+__device__ __forceinline__ void group_parts(uint32_t *gflags, const int32_t *deg, int32_t n,
+                                            int32_t split, int32_t g) {
+  const int lane = lane_id();
+  int32_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < kQ; ++k) {
+    const int32_t v = (g << kGroupShift) + k * kWave + lane;
+    const int32_t d = v < n ? deg[v] : 0;
+    sum += d < split ? d : 0;
+  }
+  sum = wave_sum(sum);
+  if (lane == 0) {
+    int32_t l = 0;
+    while (l < kMaxPartLog && (kPartEdges << l) < sum) ++l;
+    uint8_t *b = reinterpret_cast<uint8_t *>(gflags) + g;
+    *b = (uint8_t)((*b & ~(7u << kGPartShift)) | ((uint32_t)l << kGPartShift));
+  }
+}
+
+__global__ void __launch_bounds__(256) k_group_parts(uint32_t *gflags, const int32_t *deg,
+                                                     int32_t n, int32_t ngroups,
+                                                     int32_t split) {
+  const int32_t w = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+  const int32_t nw = (int32_t)(gridDim.x * blockDim.x / kWave);
+  for (int32_t g = w; g < ngroups; g += nw) group_parts(gflags, deg, n, split, g);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_group_parts_many(const RankArgs<T> *descs, int count) {
+  const int32_t w = (int32_t)(threadIdx.x / kWave);
+  for (int i = blockIdx.x; i < count; i += gridDim.x) {
+    const RankArgs<T> &A = descs[i];
+    const int32_t ng = (A.n + kGroup - 1) / kGroup;
+    for (int32_t g = w; g < ng; g += (int32_t)(blockDim.x / kWave))
+      group_parts(A.gflags, A.in_deg, A.n, A.split_min, g);
+  }
 }
 
 // Lock-free scheme, at launch: every affected long row is listed with its
@@ -1907,6 +2106,24 @@ int run_sync(dfpr_graph *g, int mode, dfpr_stats *st) {
 
 }  // namespace
 
+// The lock-free scheme sums rows of kAsyncSplitMax in-edges or more in
+// pieces whatever split_min_degree says: a claim must stay short next to a
+// sweep, since a claim that outlives the sweep it began in computes from
+// values a sweep old (with pieces disabled, one wavefront summing a
+// 25,000-edge row ended the update 1.1e-9 from the fixed point).
+constexpr int32_t kAsyncSplitMax = 8192;
+inline int32_t async_split(const dfpr_graph *g) {
+  return g->p.split_min_degree < kAsyncSplitMax ? g->p.split_min_degree : kAsyncSplitMax;
+}
+
+// Entries the lock-free worklist can hold at once: every piece, and every
+// group in its parts.  A group with s in-edges below the piece threshold
+// takes 2^l parts, 2^l < 2 * ceil(s / kPartEdges), so all groups together
+// take fewer than 2 * (ngroups + in-edge slots / kPartEdges).
+int64_t worklist_cap(const dfpr_graph *g) {
+  return 2 * ((int64_t)g->ngroups + g->in.adj_cap / kPartEdges) + g->split.pcap + 16;
+}
+
 // Sizes the piece arrays for the current adjacency capacities and
 // threshold: a row with at least split_min entries holds that many slots,
 // so at most adj_cap / split_min in-rows are long (with at most
@@ -1915,7 +2132,7 @@ int run_sync(dfpr_graph *g, int mode, dfpr_stats *st) {
 // scheme's worklist holds every group and every piece.
 int ensure_split(dfpr_graph *g) {
   Split &S = g->split;
-  int64_t lcap = g->in.adj_cap / g->p.split_min_degree + 1;
+  int64_t lcap = g->in.adj_cap / async_split(g) + 1;
   if (lcap > (int64_t)g->n + 1) lcap = (int64_t)g->n + 1;
   const int64_t pcap = g->in.adj_cap / kPiece + lcap + 1;
   int64_t xcap = g->out.adj_cap / g->p.split_min_degree + 1;
@@ -1939,7 +2156,7 @@ int ensure_split(dfpr_graph *g) {
     S.pcap = pcap;
     S.xcap = xcap;
   }
-  const int64_t gneed = (int64_t)g->ngroups + S.pcap;
+  const int64_t gneed = worklist_cap(g);
   if (gneed > g->gwl_cap) {
     DFPR_HIP(hipStreamSynchronize(g->stream));
     if (g->gwl) DFPR_HIP(hipFree(g->gwl));
@@ -1955,13 +2172,12 @@ int ensure_split(dfpr_graph *g) {
 // True when ensure_split would allocate nothing.
 bool split_ready(const dfpr_graph *g) {
   const Split &S = g->split;
-  int64_t lcap = g->in.adj_cap / g->p.split_min_degree + 1;
+  int64_t lcap = g->in.adj_cap / async_split(g) + 1;
   if (lcap > (int64_t)g->n + 1) lcap = (int64_t)g->n + 1;
   const int64_t pcap = g->in.adj_cap / kPiece + lcap + 1;
   int64_t xcap = g->out.adj_cap / g->p.split_min_degree + 1;
   if (xcap > (int64_t)g->n + 1) xcap = (int64_t)g->n + 1;
-  return lcap <= S.lcap && pcap <= S.pcap && xcap <= S.xcap &&
-         (int64_t)g->ngroups + S.pcap <= g->gwl_cap;
+  return lcap <= S.lcap && pcap <= S.pcap && xcap <= S.xcap && worklist_cap(g) <= g->gwl_cap;
 }
 
 namespace {
@@ -2002,11 +2218,14 @@ int run_async(dfpr_graph *g, dfpr_stats *st, bool all = false) {
     k_mark_all<<<grid_for(fwords, g->cu_count), 256, 0, s>>>(g->flags, fwords, g->gflags,
                                                              gwords);
   }
+  k_group_parts<<<grid_for((int64_t)g->ngroups * kWave, g->cu_count), 256, 0, s>>>(
+      g->gflags, g->in.deg, g->n, g->ngroups, async_split(g));
   k_list_long<<<grid_for(g->n, g->cu_count), 256, 0, s>>>(
-      g->flags, g->in.deg, g->n, g->p.split_min_degree, g->ctl, g->split, g->gwl);
+      g->flags, g->in.deg, g->n, async_split(g), g->ctl, g->split, g->gwl);
   k_list_groups<<<1, 256, 0, s>>>(g->gflags, g->ngroups, g->gwl, g->ctl);
   DFPR_HIP(hipGetLastError());
   RankArgs<T> A = make_args<T>(g, g->cur, g->cur);
+  A.split_min = async_split(g);
   // DF and DT updates stop by the lf_stop rule (make_args); the whole-set
   // runs (lock-free static and naive-dynamic) always at the frontier
   // tolerance
@@ -2018,9 +2237,9 @@ int run_async(dfpr_graph *g, dfpr_stats *st, bool all = false) {
   const size_t lds = lds_bytes<T>(g->p.block_size);
   int blocks = persistent_blocks(g, k_df_async<T>, lds);
   if (g->p.grid_blocks <= 0) {
-    const long long waves = async_waves(claim_chunks(g, g->h_ctl->gtail), g->cu_count);
-    const long long want = (waves + waves_per_block - 1) / waves_per_block;
-    if (want < blocks) blocks = (int)(want > 0 ? want : 1);
+    const long long want =
+        async_blocks(claim_chunks(g, g->h_ctl->gtail), g->cu_count, waves_per_block);
+    if (want < blocks) blocks = (int)want;
   }
   DFPR_HIP(hipEventRecord(g->ev[1], s));
   k_df_async<T><<<blocks, g->p.block_size, lds, s>>>(A);
@@ -2241,7 +2460,10 @@ int update_many_t(dfpr_graph *const *gs, int32_t count, dfpr_stats *stats,
     if (act[i]->stream != s) DFPR_HIP(hipStreamSynchronize(act[i]->stream));
   for (int i = 0; i < na; ++i) ++act[i]->async_epoch;
   RankArgs<T> *h = W.hdesc;
-  for (int i = 0; i < na; ++i) h[i] = make_args<T>(act[i], act[i]->cur, act[i]->cur);
+  for (int i = 0; i < na; ++i) {
+    h[i] = make_args<T>(act[i], act[i]->cur, act[i]->cur);
+    h[i].split_min = async_split(act[i]);
+  }
   // device copies: descriptors, summaries, the done counter (set to 0 by
   // k_begin_many, so nothing needs clearing beforehand)
   const size_t dbytes = sizeof(RankArgs<T>) * na;
@@ -2253,6 +2475,8 @@ int update_many_t(dfpr_graph *const *gs, int32_t count, dfpr_stats *stats,
   DFPR_HIP(hipMemcpyAsync(d_desc, h, dbytes, hipMemcpyHostToDevice, s));
   const int gb = grid_for(na, g0->cu_count);
   k_begin_many<T><<<gb, 256, 0, s>>>(d_desc, na, d_done);
+  k_group_parts_many<T><<<na < g0->cu_count * 8 ? na : g0->cu_count * 8, 256, 0, s>>>(d_desc,
+                                                                                        na);
   k_list_long_many<T><<<na < g0->cu_count * 8 ? na : g0->cu_count * 8, 256, 0, s>>>(d_desc,
                                                                                       na);
   k_list_groups_many<T><<<na < g0->cu_count * 8 ? na : g0->cu_count * 8, 256, 0, s>>>(d_desc,
@@ -2267,9 +2491,8 @@ int update_many_t(dfpr_graph *const *gs, int32_t count, dfpr_stats *stats,
   const size_t lds = lds_bytes<T>(g0->p.block_size);
   int blocks = persistent_blocks(g0, k_df_async_many<T>, lds);
   if (g0->p.grid_blocks <= 0) {
-    const long long waves = async_waves(chunks, g0->cu_count);
-    const long long want = (waves + wpb - 1) / wpb;
-    if (want < blocks) blocks = (int)(want > 0 ? want : 1);
+    const long long want = async_blocks(chunks, g0->cu_count, wpb);
+    if (want < blocks) blocks = (int)want;
   }
   const unsigned long long ticks =
       g0->p.timeout_ms > 0 ? (unsigned long long)g0->p.timeout_ms * (unsigned long long)g0->wallclock_khz

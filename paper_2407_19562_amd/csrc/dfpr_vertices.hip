@@ -146,8 +146,8 @@ int add_vertices(dfpr_graph *g, int32_t count, int32_t *first_id) {
   const size_t gb0 = flag_bytes(ng0);
   DFPR_HIP(hipMemsetAsync(reinterpret_cast<uint8_t *>(g->gflags) + ng0, 0, gb0 - ng0, s));
   if ((rc = grow_t(g, &g->gflags, gb0, flag_bytes(ng1), 0))) return rc;
-  if ((rc = grow_t(g, &g->gwl, g->gwl_cap * 4, (ng1 + g->split.pcap) * 4, 0xFF))) return rc;
-  g->gwl_cap = ng1 + g->split.pcap;
+  // the worklist is sized again for the new group count by ensure_split
+  // below; until then it keeps its entries (all -1 between updates)
   if ((rc = grow_t(g, &g->wl, n0 * 4, n1 * 4, 0xFF))) return rc;
   if ((rc = grow_t(g, &g->steps, (n0 + 1) * 4, (n1 + 1) * 4, -1))) return rc;
   // tile sums are rebuilt by every update
