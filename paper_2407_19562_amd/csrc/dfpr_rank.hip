@@ -133,6 +133,8 @@ constexpr int kUnroll = 6;
 template <typename T>
 struct WaveLds {
   int32_t pre[kRows + 1];
+  int32_t vbuf[kRows];  // lock-free scheme: affected vertices gathered from
+                        // the claimed group parts, processed 256 at a time
   int64_t off[kRows];
   double acc[kRows];  // fp64 sums (fp64 ranks; fp32 rows at/above the
                       // compensation threshold)
@@ -683,40 +685,70 @@ __device__ __forceinline__ void release_mark(const RankArgs<T> &A, WaveSched &ws
   ws.moved = false;
 }
 
-// Processes one worklist entry in place: the affected vertices of a group
-// part, or a piece of an affected long row.  One wavefront.
+// Processes the worklist entries [b, e) of a claim in place, one wavefront.
+// Pieces of long rows are summed one by one.  The affected vertices of the
+// group parts are gathered, in order, into steps of up to 256 vertices: the
+// parts of a frontier are sparse (on the road-like grid a quarter of a
+// part's ids are affected), and each step costs a chain of dependent memory
+// round trips however few vertices it holds.
 template <typename T>
-__device__ __forceinline__ void process_entry(const RankArgs<T> &A, WaveLds<T> &L,
-                                              unsigned long long gp, Counters &cnt,
-                                              long long &newly, bool &moved) {
+__device__ __forceinline__ void process_claim(const RankArgs<T> &A, WaveLds<T> &L,
+                                              unsigned long long b, unsigned long long e,
+                                              Counters &cnt, long long &newly, bool &moved) {
   const int lane = lane_id();
+  const uint64_t below = lanemask_lt();
   double unused = 0.0;
-  int32_t x = -1;
-  if (lane == 0) x = load_agent(A.gwl + gp);
-  x = __builtin_amdgcn_readfirstlane(x);
-  if (x == -1) {
-    // slot reserved, entry not yet stored: its appender still holds a
-    // mark; count it as work left all the same
-    moved = true;
-    return;
-  }
-  if (x <= -2) {  // a piece of an affected long row
-    process_piece<T, kAsync>(A, L, -x - 2, cnt, unused, newly, moved);
-    return;
-  }
-  // a part of a group: its vertex range of 256 >> l ids
-  const int32_t l = (x >> kEntryLogShift) & 7;
-  const int32_t span = kGroup >> l;
-  const int32_t v0 = ((x & kEntryGroupMask) << kGroupShift) +
-                     ((x >> kEntryPartShift) & 15) * span;
-  int32_t vv[kQ];
+  int32_t nbuf = 0;  // vertices gathered (the same in every lane)
+  auto flush = [&]() {
+    if (nbuf == 0) return;
+    wave_lds_fence();
+    int32_t vv[kQ];
 #pragma unroll
-  for (int k = 0; k < kQ; ++k) {
-    const int32_t o = k * kWave + lane;
-    const int32_t v = v0 + o;
-    vv[k] = (o < span && v < A.n && (flag_byte(A.flags, v, true) & kVA)) ? v : -1;
+    for (int k = 0; k < kQ; ++k) {
+      const int32_t pos = k * kWave + lane;
+      vv[k] = pos < nbuf ? L.vbuf[pos] : -1;
+    }
+    wave_lds_fence();
+    process_step<T, kAsync>(A, L, vv, cnt, unused, newly, moved);
+    nbuf = 0;
+  };
+  for (unsigned long long gp = b; gp < e; ++gp) {
+    int32_t x = -1;
+    if (lane == 0) x = load_agent(A.gwl + gp);
+    x = __builtin_amdgcn_readfirstlane(x);
+    if (x == -1) {
+      // slot reserved, entry not yet stored: its appender still holds a
+      // mark; count it as work left all the same
+      moved = true;
+      continue;
+    }
+    if (x <= -2) {  // a piece of an affected long row
+      process_piece<T, kAsync>(A, L, -x - 2, cnt, unused, newly, moved);
+      continue;
+    }
+    // a part of a group: its vertex range of 256 >> l ids
+    const int32_t l = (x >> kEntryLogShift) & 7;
+    const int32_t span = kGroup >> l;
+    const int32_t v0 = ((x & kEntryGroupMask) << kGroupShift) +
+                       ((x >> kEntryPartShift) & 15) * span;
+    bool aff[kQ];
+    int32_t total = 0;
+#pragma unroll
+    for (int k = 0; k < kQ; ++k) {
+      const int32_t o = k * kWave + lane;
+      const int32_t v = v0 + o;
+      aff[k] = o < span && v < A.n && (flag_byte(A.flags, v, true) & kVA);
+      total += __popcll(__ballot(aff[k]));
+    }
+    if (nbuf + total > kRows) flush();
+#pragma unroll
+    for (int k = 0; k < kQ; ++k) {
+      const uint64_t m = __ballot(aff[k]);
+      if (aff[k]) L.vbuf[nbuf + __popcll(m & below)] = v0 + k * kWave + lane;
+      nbuf += __popcll(m);
+    }
   }
-  process_step<T, kAsync>(A, L, vv, cnt, unused, newly, moved);
+  flush();
 }
 
 // Idle backoff: 64 * 2^min(idle, 4) sleep units, so workgroups without work
@@ -805,10 +837,12 @@ __device__ int df_async_step(const RankArgs<T> &A, WaveLds<T> &L, Counters &cnt,
     return code;
   }
   ws.idle = 0;
-  const unsigned w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  // wavefront w takes the w-th run of `per` entries (neighbouring groups)
+  const unsigned long long w = threadIdx.x / kWave;
+  const unsigned long long b = p + w * per < end ? p + w * per : end;
+  const unsigned long long e = b + per < end ? b + per : end;
   bool moved = false;
-  for (unsigned long long gp = p + w; gp < end; gp += nw)
-    process_entry<T>(A, L, gp, cnt, newly, moved);
+  process_claim<T>(A, L, b, e, cnt, newly, moved);
   // every store of this claim (ranks, contributions, flags, worklist
   // entries), by every wavefront, is performed before the workgroup's next
   // operation on the scheduling word, which gives its mark back
