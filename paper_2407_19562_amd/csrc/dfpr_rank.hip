@@ -128,13 +128,27 @@ constexpr int kRows = kQ * kWave;
 // and 8 were 1-3% slower)
 constexpr int kUnroll = 6;
 
+// Edge positions of a step covered by the owner bitmap (steps of the
+// barrier-based scheme stay below 16384 plus one row under the piece
+// threshold; longer ones fall back to a binary search).
+constexpr int32_t kBitCap = 20480;
+constexpr int32_t kBitWords = kBitCap / 32;
+
+struct BitWord {
+  uint32_t bits;  // bit b: a non-empty row starts at edge position 32 w + b
+  uint32_t cnt;   // rows starting before word w
+};
+
 // Per-wavefront LDS: the flattened edge list of the current step (prefix of
-// the row lengths and the row starts) and per-row accumulators.
+// the row lengths and the row starts), the owner bitmap, and per-row
+// accumulators.
+
 template <typename T>
 struct WaveLds {
   int32_t pre[kRows + 1];
   int32_t vbuf[kRows];  // lock-free scheme: affected vertices gathered from
                         // the claimed group parts, processed 256 at a time
+  BitWord bm[kBitWords];  // owner bitmap of the step's edge positions
   int64_t off[kRows];
   double acc[kRows];  // fp64 sums (fp64 ranks; fp32 rows at/above the
                       // compensation threshold)
@@ -208,6 +222,65 @@ __device__ __forceinline__ int32_t flatten_rows(WaveLds<T> &L, const int64_t *of
   return base;
 }
 
+// Publishes the non-empty rows among the step's 256 (off, len), in order,
+// as one flattened range in LDS: pre[k] and off[k] for the k-th non-empty
+// row, pre[k] = total beyond them; rank[q] (per lane) is the position of the
+// lane's q-th row among them, or -1.  Clears the accumulators.  When the
+// range fits kBitCap it also builds the owner bitmap: the row owning edge e
+// is then cnt[e / 32] + (set bits of bits[e / 32] at or below e % 32) - 1,
+// two LDS reads where a binary search over 256 rows took eight dependent
+// ones (about a fifth of a barrier-based iteration on the 2^22 R-MAT).
+template <typename T>
+__device__ __forceinline__ int32_t flatten_nonempty(WaveLds<T> &L, const int64_t *off,
+                                                   const int32_t *len, int32_t *rank) {
+  const int lane = lane_id();
+  wave_lds_fence();
+  int32_t base = 0, nbase = 0;
+  int32_t start[kQ];
+#pragma unroll
+  for (int k = 0; k < kQ; ++k) {
+    const int32_t incl = wave_incl_scan(len[k]);
+    const bool ne = len[k] > 0;
+    const int32_t nincl = wave_incl_scan(ne ? 1 : 0);
+    start[k] = base + incl - len[k];
+    rank[k] = ne ? nbase + nincl - 1 : -1;
+    if (ne) {
+      L.pre[rank[k]] = start[k];
+      L.off[rank[k]] = off[k];
+    }
+    base += __shfl(incl, kWave - 1);
+    nbase += __shfl(nincl, kWave - 1);
+  }
+  const int32_t total = base, nnz = nbase;
+  for (int32_t r = nnz + lane; r <= kRows; r += kWave) L.pre[r] = total;
+  for (int32_t r = lane; r < nnz; r += kWave) {
+    L.acc[r] = 0.0;
+    if constexpr (sizeof(T) == 4) L.accf[r] = 0.f;
+  }
+  if (total <= kBitCap) {
+    const int32_t words = (total + 31) >> 5;
+    for (int32_t w = lane; w < words; w += kWave) L.bm[w].bits = 0u;
+    wave_lds_fence();
+#pragma unroll
+    for (int k = 0; k < kQ; ++k)
+      if (rank[k] >= 0) atomicOr(&L.bm[start[k] >> 5].bits, 1u << (start[k] & 31));
+    wave_lds_fence();
+    // counts before each word: each lane a run of consecutive words
+    const int32_t per = (words + kWave - 1) / kWave;
+    const int32_t w0 = lane * per;
+    const int32_t w1 = w0 + per < words ? w0 + per : words;
+    int32_t mine = 0;
+    for (int32_t w = w0; w < w1; ++w) mine += __popc(L.bm[w].bits);
+    int32_t run = wave_incl_scan(mine) - mine;
+    for (int32_t w = w0; w < w1; ++w) {
+      L.bm[w].cnt = (uint32_t)run;
+      run += __popc(L.bm[w].bits);
+    }
+  }
+  wave_lds_fence();
+  return total;
+}
+
 // Sums over the in-rows of the step's 256 vertices, edge-parallel: every
 // round loads kUnroll x 64 row entries, then as many contributions, all
 // independent, and adds them to the owners' LDS accumulators.  The rounds
@@ -219,7 +292,9 @@ __device__ __forceinline__ void gather_flat(const RankArgs<T> &A, WaveLds<T> &L,
                                             const int64_t *off,
                                             const int32_t *deg, double *sum) {
   const int lane = lane_id();
-  const int32_t total = flatten_rows(L, off, deg);
+  int32_t rank[kQ];
+  const int32_t total = flatten_nonempty(L, off, deg, rank);
+  const bool bitmap = total <= kBitCap;
   int own[kUnroll];
   int32_t idx[kUnroll];
   // Owners and row entries of the round starting at edge `base` (called
@@ -233,7 +308,13 @@ __device__ __forceinline__ void gather_flat(const RankArgs<T> &A, WaveLds<T> &L,
     for (int j = 0; j < kUnroll; ++j) {
       const int32_t e = base + j * kWave + lane;
       const int32_t ec = e < total ? e : total - 1;
-      const int o = find_owner(L.pre, ec);
+      int o;
+      if (bitmap) {
+        const BitWord bw = L.bm[ec >> 5];
+        o = (int)bw.cnt + __popc(bw.bits & ((2u << (ec & 31)) - 1u)) - 1;
+      } else {
+        o = find_owner(L.pre, ec);
+      }
       idx[j] = A.in_adj[L.off[o] + (ec - L.pre[o])];
       own[j] = e < total ? o : -1;
     }
@@ -266,9 +347,9 @@ __device__ __forceinline__ void gather_flat(const RankArgs<T> &A, WaveLds<T> &L,
   wave_lds_fence();
 #pragma unroll
   for (int k = 0; k < kQ; ++k) {
-    const int r = k * kWave + lane;
-    sum[k] = L.acc[r];
-    if constexpr (sizeof(T) == 4) sum[k] += (double)L.accf[r];
+    const int r = rank[k];
+    sum[k] = r >= 0 ? L.acc[r] : 0.0;
+    if constexpr (sizeof(T) == 4) sum[k] += r >= 0 ? (double)L.accf[r] : 0.0;
   }
 }
 
