@@ -333,7 +333,11 @@ __device__ __forceinline__ void gather_flat(const RankArgs<T> &A, WaveLds<T> &L,
 #pragma unroll
     for (int j = 0; j < kUnroll; ++j) {
       if (cur[j] < 0) continue;
-      if constexpr (sizeof(T) == 8) {
+      if constexpr (sizeof(T) == 8 || COH) {
+        // lock-free scheme, fp32 ranks: every row in fp64 as well.  fp32
+        // atomics add in arrival order, so a row's rounded sum can differ
+        // by ulps from one sweep to the next, and a rank that keeps moving
+        // by two ulps never meets the stopping rule
         atomicAdd(&L.acc[cur[j]], (double)c[j]);
       } else {
         const int32_t dlen = L.pre[cur[j] + 1] - L.pre[cur[j]];
