@@ -444,7 +444,8 @@ def grid(args, torch, dfpr, inputs):
             log(f"{key}: {out[key]} roofline {roof[key]}")
     return {"metric": METRIC, "workload": "grid4096", "unit": "ms",
             "config": {"workload": desc, "batch": "1e-4*|E| (80/20), 5 in sequence"},
-            "results": out, "roofline": roof["sync_fp64"], "roofline_all": roof}
+            "results": out, "roofline": roof["sync_fp64"], "roofline_all": roof,
+            "copy_peak_gbs": copy_peak_gbs(torch, dfpr)}
 
 
 def faults(args, torch, dfpr, inputs):
