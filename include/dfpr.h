@@ -111,11 +111,15 @@ typedef struct {
   int32_t chunk;         /* lock-free scheme: vertices per wavefront of a
                             claim, whole 256-vertex groups (chunk / 256, at
                             least one); a multiple of 64 in [64, 4096], or
-                            0 (default): one group per 2048 groups of the
-                            graph, 1..8.  A claim is made by a whole
-                            workgroup, for all its wavefronts             */
-  int32_t block_size;    /* threads per workgroup: 64, 128 (default), 192 or
-                            256                                             */
+                            0 (default): one group per 1024 groups of the
+                            graph, 1..16, and 16 groups in the batched
+                            launch.  A claim is made by a whole workgroup,
+                            for all its wavefronts                         */
+  int32_t block_size;    /* threads per workgroup of the rank kernel: 64,
+                            128, 192 or 256, or 0 (default): 128 for the
+                            barrier-based scheme, 256 for the lock-free
+                            scheme on one graph, 64 for the batched launch
+                            (dfpr_update_many takes the first graph's)     */
   int32_t reorder;       /* internal vertex order, fixed at creation:
                             0 keep the caller's ids; 1 sort by decreasing
                             out-degree, so the contributions read most often
@@ -130,8 +134,8 @@ typedef struct {
   int32_t grid_blocks;   /* workgroups of the rank kernels; 0 = automatic:
                             barrier-based, at most 12 wavefronts per CU and
                             no more than an iteration's work items;
-                            lock-free, about four claims per wavefront per
-                            sweep                                           */
+                            lock-free, about four claims per workgroup per
+                            sweep and at least four wavefronts per CU      */
   int32_t graph_replay;  /* barrier-based loop: 0 one launch sequence per
                             iteration from the host; 1 two iterations
                             captured once in a HIP graph and replayed (kernel

@@ -16,7 +16,8 @@ Spaces:
           the vertex-to-wavefront mapping (split_min_degree: rows below it
           share a wavefront's 256-vertex step, rows at or above it get one
           wavefront per 4096-edge piece), groups per claim (chunk / 256;
-          0 = the library's choice) and the workgroup size.
+          0 = the library's choice) and the workgroup size (0 = the
+          library's choice).
 
 A trial that ends at the sweep cap (or fails) disqualifies its parameter
 set.  Winners are cached per graph-shape bucket (scheme, precision, graph
@@ -43,7 +44,7 @@ SPACES = {
              for s in (1024, 2048, 4096) for b in (128, 256)],
     "async": [{"split_min_degree": s, "chunk": c, "block_size": b}
               for s in (512, 2048, 8192)
-              for c in (0, 256, 1024, 4096) for b in (64, 128, 256)],
+              for c in (0, 1024, 4096) for b in (0, 64, 128, 256)],
 }
 
 

@@ -62,11 +62,13 @@ int check_params(const dfpr_params *p) {
   if (p->kahan_min_degree < 0) return fail(DFPR_EINVAL, "kahan_min_degree must be >= 0");
   if (p->chunk != 0 && (p->chunk < 64 || p->chunk % 64 || p->chunk > 4096))
     return fail(DFPR_EINVAL, "chunk must be 0 or a multiple of 64 in [64, 4096]");
-  if (p->block_size < 64 || p->block_size > 256 || p->block_size % 64)
-    return fail(DFPR_EINVAL, "block_size must be 64, 128, 192 or 256");
+  if (p->block_size != 0 && (p->block_size < 64 || p->block_size > 256 || p->block_size % 64))
+    return fail(DFPR_EINVAL, "block_size must be 0, 64, 128, 192 or 256");
   if (p->timeout_ms < 0) return fail(DFPR_EINVAL, "timeout_ms must be >= 0");
   if (p->reorder < 0 || p->reorder > 2) return fail(DFPR_EINVAL, "reorder must be 0, 1 or 2");
-  if (p->grid_blocks < 0 || (int64_t)p->grid_blocks * (p->block_size / 64) > 32768)
+  // block_size 0: the library's choice, at most 256 threads
+  const int64_t waves = (p->block_size > 0 ? p->block_size : 256) / 64;
+  if (p->grid_blocks < 0 || (int64_t)p->grid_blocks * waves > 32768)
     return fail(DFPR_EINVAL, "grid_blocks * waves per block must be <= 32768");
   if (p->graph_replay < 0 || p->graph_replay > 2)
     return fail(DFPR_EINVAL, "graph_replay must be 0, 1 or 2");
@@ -178,7 +180,7 @@ int dfpr_params_default(dfpr_params *p) {
   p->kahan_min_degree = 64;
   p->split_min_degree = 2048;
   p->chunk = 0;
-  p->block_size = 128;
+  p->block_size = 0;
   p->reorder = 2;
   p->renormalize = 0;
   p->timeout_ms = 60000;

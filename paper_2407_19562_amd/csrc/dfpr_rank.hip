@@ -770,9 +770,11 @@ __device__ __forceinline__ void release_mark(const RankArgs<T> &A, WaveSched &ws
   ws.moved = false;
 }
 
+constexpr int kScan = 16;  // worklist entries read at once (a claim holds at most 16)
+
 // Processes the worklist entries [b, e) of a claim in place, one wavefront.
 // Pieces of long rows are summed one by one.  The affected vertices of the
-// group parts are gathered, in order, into steps of up to 256 vertices: the
+// group parts are gathered into steps of up to 256 vertices: the
 // parts of a frontier are sparse (on the road-like grid a quarter of a
 // part's ids are affected), and each step costs a chain of dependent memory
 // round trips however few vertices it holds.
@@ -797,40 +799,73 @@ __device__ __forceinline__ void process_claim(const RankArgs<T> &A, WaveLds<T> &
     process_step<T, kAsync>(A, L, vv, cnt, unused, newly, moved);
     nbuf = 0;
   };
-  for (unsigned long long gp = b; gp < e; ++gp) {
-    int32_t x = -1;
-    if (lane == 0) x = load_agent(A.gwl + gp);
-    x = __builtin_amdgcn_readfirstlane(x);
-    if (x == -1) {
-      // slot reserved, entry not yet stored: its appender still holds a
-      // mark; count it as work left all the same
-      moved = true;
-      continue;
-    }
-    if (x <= -2) {  // a piece of an affected long row
-      process_piece<T, kAsync>(A, L, -x - 2, cnt, unused, newly, moved);
-      continue;
-    }
-    // a part of a group: its vertex range of 256 >> l ids
-    const int32_t l = (x >> kEntryLogShift) & 7;
-    const int32_t span = kGroup >> l;
-    const int32_t v0 = ((x & kEntryGroupMask) << kGroupShift) +
-                       ((x >> kEntryPartShift) & 15) * span;
-    bool aff[kQ];
-    int32_t total = 0;
+  // entries are read kScan at a time, and the flag words of all their
+  // group parts are loaded before any is used: two memory round trips per
+  // kScan entries instead of two per entry
+  for (unsigned long long g0 = b; g0 < e; g0 += kScan) {
+    const int32_t ne = (int32_t)(e - g0 < (unsigned long long)kScan ? e - g0 : kScan);
+    const int32_t xl = lane < ne ? load_agent(A.gwl + g0 + lane) : -1;
+    // one 32-bit flag word per lane: the flags of the part's vertices
+    // v0 + 4 lane .. v0 + 4 lane + 3 (a part spans 16 to 256 ids)
+    auto flag_word = [&](int32_t x) -> uint32_t {
+      if (x < 0) return 0u;
+      const int32_t l = (x >> kEntryLogShift) & 7;
+      const int32_t span = kGroup >> l;
+      const int32_t v0 = ((x & kEntryGroupMask) << kGroupShift) +
+                         ((x >> kEntryPartShift) & 15) * span;
+      const int32_t v = v0 + 4 * lane;
+      return 4 * lane < span && v < A.n ? load_agent(A.flags + (v >> 2)) : 0u;
+    };
+    uint32_t fw[kScan];
 #pragma unroll
-    for (int k = 0; k < kQ; ++k) {
-      const int32_t o = k * kWave + lane;
-      const int32_t v = v0 + o;
-      aff[k] = o < span && v < A.n && (flag_byte(A.flags, v, true) & kVA);
-      total += __popcll(__ballot(aff[k]));
-    }
-    if (nbuf + total > kRows) flush();
+    for (int j = 0; j < kScan; ++j)
+      fw[j] = j < ne ? flag_word(__builtin_amdgcn_readlane(xl, j)) : 0u;
 #pragma unroll
-    for (int k = 0; k < kQ; ++k) {
-      const uint64_t m = __ballot(aff[k]);
-      if (aff[k]) L.vbuf[nbuf + __popcll(m & below)] = v0 + k * kWave + lane;
-      nbuf += __popcll(m);
+    for (int j = 0; j < kScan; ++j) {
+      if (j >= ne) break;
+      int32_t x = __builtin_amdgcn_readlane(xl, j);
+      uint32_t f = fw[j];
+      if (x == -1) {
+        // slot reserved, entry not yet stored when the batch was read
+        // (appends at the tail race with claims there): read it again
+        x = lane == 0 ? load_agent(A.gwl + g0 + j) : -1;
+        x = __builtin_amdgcn_readfirstlane(x);
+        if (x == -1) {
+          // still not stored: its appender holds a mark; count it as work
+          // left all the same
+          moved = true;
+          continue;
+        }
+        f = flag_word(x);
+      }
+      if (x <= -2) {  // a piece of an affected long row
+        process_piece<T, kAsync>(A, L, -x - 2, cnt, unused, newly, moved);
+        continue;
+      }
+      const int32_t l = (x >> kEntryLogShift) & 7;
+      const int32_t span = kGroup >> l;
+      const int32_t v0 = ((x & kEntryGroupMask) << kGroupShift) +
+                         ((x >> kEntryPartShift) & 15) * span;
+      const int32_t v = v0 + 4 * lane;
+      // affected vertices in id order (consecutive rows keep their edges
+      // contiguous for the gather): a lane's count (0..4) is summed over
+      // the lanes below it bit by bit, one ballot per bit
+      bool aff[4];
+      uint32_t c = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        aff[i] = v + i < A.n && ((f >> (8 * i)) & kVA);
+        c += aff[i] ? 1u : 0u;
+      }
+      const uint64_t m0 = __ballot(c & 1u), m1 = __ballot(c & 2u), m2 = __ballot(c & 4u);
+      const int32_t total = __popcll(m0) + 2 * __popcll(m1) + 4 * __popcll(m2);
+      if (nbuf + total > kRows) flush();
+      int32_t pos = nbuf + __popcll(m0 & below) + 2 * __popcll(m1 & below) +
+                    4 * __popcll(m2 & below);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (aff[i]) L.vbuf[pos++] = v + i;
+      nbuf += total;
     }
   }
   flush();
@@ -1495,11 +1530,34 @@ inline int grid_for(int64_t work, int cu) {
 // workgroup ran 1.6x faster than claims of 4 by single wavefronts, which
 // had run 2.5x faster than claims of one (every claim is an atomic on the
 // one scheduling word, and idle workgroups poll it).
-inline int effective_chunk(const dfpr_graph *g) {
+// Which launch a default launch parameter is chosen for.
+enum LaunchKind { kLaunchSync = 0, kLaunchAsync = 1, kLaunchMany = 2 };
+
+// Vertices per wavefront of a lock-free claim.  Default, one graph: one
+// 256-vertex group per 1024 groups of the graph, 1..16 (claims are costly
+// next to the work of a small graph's sweep, and too few per sweep leave
+// the device idle on a small one: the 2^14 R-MAT ran 10x slower with 16
+// groups per wavefront than with one, the 2^22 R-MAT and the 4096 x 4096
+// grid fastest with 16, which 32 made slower again).  Batched launch: 16
+// groups, as the many graphs keep the device busy (measured 1.8x faster
+// than one group per wavefront over 1024 graphs of 1e3..1e6 edges).
+inline int effective_chunk(const dfpr_graph *g, int kind = kLaunchAsync) {
   if (g->p.chunk > 0) return g->p.chunk;
-  int per = g->ngroups / 2048;
-  per = per < 1 ? 1 : (per > 8 ? 8 : per);
+  if (kind == kLaunchMany) return 16 * kGroup;
+  int per = g->ngroups / 1024;
+  per = per < 1 ? 1 : (per > 16 ? 16 : per);
   return per * kGroup;
+}
+
+// Threads per workgroup of the rank kernel: the block_size parameter, or
+// by default 128 for the barrier-based scheme (256 was as fast on the large
+// graphs and 9% slower on the 2^14 R-MAT), 256 for the lock-free scheme on
+// one graph (a claim serves four wavefronts: the grid update took 4.4 ms
+// against 5.0 ms with 128), 64 for the batched launch (its autotuned
+// choice with 16-group claims).
+inline int block_for(const dfpr_graph *g, int kind) {
+  if (g->p.block_size > 0) return g->p.block_size;
+  return kind == kLaunchSync ? 128 : (kind == kLaunchAsync ? 256 : 64);
 }
 
 // Lock-free grid: enough workgroups that each takes about kChunksPerWave
@@ -1510,8 +1568,9 @@ inline int effective_chunk(const dfpr_graph *g) {
 // wavefront claiming than with a quarter of them).
 constexpr int kChunksPerWave = 4;
 
-inline long long claim_chunks(const dfpr_graph *g, unsigned long long gtail) {
-  const long long per = effective_chunk(g) / kGroup;
+inline long long claim_chunks(const dfpr_graph *g, unsigned long long gtail,
+                              int kind = kLaunchAsync) {
+  const long long per = effective_chunk(g, kind) / kGroup;
   return ((long long)gtail + per - 1) / per;
 }
 
@@ -1583,17 +1642,17 @@ RankArgs<T> make_args(dfpr_graph *g, int rd, int wr) {
 // field of the scheduling word holds 16 bits, so the grid stays below 32768
 // wavefronts; chunk <= 4096 keeps cursor overshoot far below 2^32.
 template <typename K>
-int persistent_blocks(dfpr_graph *g, K kernel, size_t lds) {
+int persistent_blocks(dfpr_graph *g, K kernel, size_t lds, int block) {
   int blocks = g->p.grid_blocks;
   if (blocks <= 0) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel,
-                                                     g->p.block_size, lds) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, lds) !=
+            hipSuccess ||
         per_cu < 1)
       per_cu = 1;
     blocks = per_cu * g->cu_count;
   }
-  const int max_blocks = 32768 / (g->p.block_size / kWave);
+  const int max_blocks = 32768 / (block / kWave);
   return blocks > max_blocks ? max_blocks : blocks;
 }
 
@@ -2051,8 +2110,9 @@ int replay_graph(dfpr_graph *g, int mode, int blocks, size_t lds, F &launch_iter
                         g->sync_max, g->sync_len, g->split.xrow, g->out.off,
                         g->out.deg, g->out.adj, g->in.deg};
   key = fnv1a(key, ptrs, sizeof(ptrs));
-  const int64_t vals[] = {blocks, (int64_t)lds, g->p.block_size, g->p.split_min_degree,
-                          g->p.max_iters, g->n, g->cu_count, (int64_t)sizeof(T)};
+  const int64_t vals[] = {blocks, (int64_t)lds, block_for(g, kLaunchSync),
+                          g->p.split_min_degree, g->p.max_iters, g->n, g->cu_count,
+                          (int64_t)sizeof(T)};
   key = fnv1a(key, vals, sizeof(vals));
   double tol = g->p.tol;
   key = fnv1a(key, &tol, sizeof(tol));
@@ -2108,13 +2168,14 @@ int run_sync(dfpr_graph *g, int mode, dfpr_stats *st) {
   k_sync_begin<<<4, 256, 0, s>>>(g->ctl, g->sync_max, g->sync_grab, g->sync_len, iters);
   DFPR_HIP(hipGetLastError());
   auto kern = mode == kAll ? k_sync_iter<T, kAll> : k_sync_iter<T, kSyncDF>;
-  const size_t lds = lds_bytes<T>(g->p.block_size);
-  int blocks = persistent_blocks(g, kern, lds);
+  const int block = block_for(g, kLaunchSync);
+  const size_t lds = lds_bytes<T>(block);
+  int blocks = persistent_blocks(g, kern, lds, block);
   if (g->p.grid_blocks <= 0) {
     // no more wavefronts than an iteration can have items (tiles, edge
     // steps, pieces), and at most kSyncWavesPerCU per CU: measured on the
     // 2^22 R-MAT with the pipelined gather, 12 per CU beat 8, 10, 14 and 16
-    const int wpb = g->p.block_size / kWave;
+    const int wpb = block / kWave;
     const int64_t items = 2 * (((int64_t)g->n + kRows - 1) / kRows) +
                           g->in.adj_cap / kStepEdges + 1 + g->split.pcap;
     int64_t want = (items + wpb - 1) / wpb;
@@ -2130,7 +2191,7 @@ int run_sync(dfpr_graph *g, int mode, dfpr_stats *st) {
   auto launch_iteration = [&](int parity, hipStream_t q, hipEvent_t e0, hipEvent_t e1) {
     RankArgs<T> A = make_args<T>(g, parity, parity ^ 1);
     if (e0) (void)hipEventRecord(e0, q);
-    kern<<<blocks, g->p.block_size, lds, q>>>(A, g->steps);
+    kern<<<blocks, block, lds, q>>>(A, g->steps);
     if (e1) (void)hipEventRecord(e1, q);
     if (mode != kAll) {
       k_expand_long<<<xgrid, 256, 0, q>>>(g->split.xrow, g->out.off, g->out.deg,
@@ -2352,16 +2413,17 @@ int run_async(dfpr_graph *g, dfpr_stats *st, bool all = false) {
   // grid from the groups listed by the marking (kChunksPerWave)
   DFPR_HIP(hipMemcpyAsync(g->h_ctl, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
   DFPR_HIP(hipStreamSynchronize(s));
-  const int waves_per_block = g->p.block_size / kWave;
-  const size_t lds = lds_bytes<T>(g->p.block_size);
-  int blocks = persistent_blocks(g, k_df_async<T>, lds);
+  const int block = block_for(g, kLaunchAsync);
+  const int waves_per_block = block / kWave;
+  const size_t lds = lds_bytes<T>(block);
+  int blocks = persistent_blocks(g, k_df_async<T>, lds, block);
   if (g->p.grid_blocks <= 0) {
     const long long want =
         async_blocks(claim_chunks(g, g->h_ctl->gtail), g->cu_count, waves_per_block);
     if (want < blocks) blocks = (int)want;
   }
   DFPR_HIP(hipEventRecord(g->ev[1], s));
-  k_df_async<T><<<blocks, g->p.block_size, lds, s>>>(A);
+  k_df_async<T><<<blocks, block, lds, s>>>(A);
   DFPR_HIP(hipGetLastError());
   DFPR_HIP(hipEventRecord(g->ev[2], s));
   k_zero_lcnt<<<grid_for(g->split.lcap, g->cu_count), 256, 0, s>>>(g->split.lcnt, g->ctl);
@@ -2582,6 +2644,7 @@ int update_many_t(dfpr_graph *const *gs, int32_t count, dfpr_stats *stats,
   for (int i = 0; i < na; ++i) {
     h[i] = make_args<T>(act[i], act[i]->cur, act[i]->cur);
     h[i].split_min = async_split(act[i]);
+    h[i].chunk = effective_chunk(act[i], kLaunchMany);
   }
   // device copies: descriptors, summaries, the done counter (set to 0 by
   // k_begin_many, so nothing needs clearing beforehand)
@@ -2605,10 +2668,11 @@ int update_many_t(dfpr_graph *const *gs, int32_t count, dfpr_stats *stats,
   DFPR_HIP(hipMemcpyAsync(hs, d_sum, sbytes, hipMemcpyDeviceToHost, s));
   DFPR_HIP(hipStreamSynchronize(s));
   long long chunks = 0;
-  for (int i = 0; i < na; ++i) chunks += claim_chunks(act[i], hs[i].gtail);
-  const int wpb = g0->p.block_size / kWave;
-  const size_t lds = lds_bytes<T>(g0->p.block_size);
-  int blocks = persistent_blocks(g0, k_df_async_many<T>, lds);
+  for (int i = 0; i < na; ++i) chunks += claim_chunks(act[i], hs[i].gtail, kLaunchMany);
+  const int block = block_for(g0, kLaunchMany);
+  const int wpb = block / kWave;
+  const size_t lds = lds_bytes<T>(block);
+  int blocks = persistent_blocks(g0, k_df_async_many<T>, lds, block);
   if (g0->p.grid_blocks <= 0) {
     const long long want = async_blocks(chunks, g0->cu_count, wpb);
     if (want < blocks) blocks = (int)want;
@@ -2617,7 +2681,7 @@ int update_many_t(dfpr_graph *const *gs, int32_t count, dfpr_stats *stats,
       g0->p.timeout_ms > 0 ? (unsigned long long)g0->p.timeout_ms * (unsigned long long)g0->wallclock_khz
                            : 0ull;
   DFPR_HIP(hipEventRecord(g0->ev[0], s));
-  k_df_async_many<T><<<blocks, g0->p.block_size, lds, s>>>(d_desc, na, d_done, &g0->ctl->abort,
+  k_df_async_many<T><<<blocks, block, lds, s>>>(d_desc, na, d_done, &g0->ctl->abort,
                                                          ticks);
   DFPR_HIP(hipGetLastError());
   DFPR_HIP(hipEventRecord(g0->ev[1], s));

@@ -116,12 +116,12 @@ def test_invalid_parameters_are_rejected_before_any_device_call(lib, field, valu
 
 
 def test_automatic_chunk_and_grid_are_valid(lib):
-    # chunk 0 and grid_blocks 0 (the defaults) pass validation: on a host
+    # chunk, grid_blocks and block_size 0 (the defaults) pass validation: on a host
     # without a device the call fails later, with a device error
     h = lib._lib()
     out = ctypes.c_void_p()
     p = lib.dfpr_params_default()
-    assert p.chunk == 0 and p.grid_blocks == 0 and p.block_size == 128
+    assert p.chunk == 0 and p.grid_blocks == 0 and p.block_size == 0
     rc = h.dfpr_graph_create(4, 0, None, None, 0, ctypes.byref(p), None, ctypes.byref(out))
     assert rc != lib.DFPR_EINVAL
     if rc == lib.DFPR_OK:

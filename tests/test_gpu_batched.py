@@ -1,7 +1,10 @@
 """Many graphs' updates in one persistent launch (dfpr_update_many):
 every graph's ranks must match its own oracle, and the same update run
-alone must agree within the same tolerance (the lock-free schedule is
-nondeterministic, so results are compared to tolerance, not bit-exact)."""
+alone must agree with it (the lock-free schedule is nondeterministic, so
+results are compared to tolerance, not bit-exact: within the bar once the
+stopping error along the rank-mass direction is taken out, and within twice
+the bar as a whole, since each is within the bar of the fixed point; see
+agreement.py)."""
 import sys
 
 import numpy as np
@@ -9,6 +12,7 @@ import pytest
 
 pytestmark = pytest.mark.gpu
 
+from agreement import agree
 from paper_2407_19562_amd import inputs
 
 FP64_TOL = 1e-9
@@ -69,11 +73,14 @@ def test_update_many_matches_oracle_and_alone(D, O, prec):
             assert st.converged and st.sweeps > 0
             if prec == 64:
                 assert np.abs(R - ref).max() < FP64_TOL
-                assert np.abs(R - a).max() < FP64_TOL
+                ok, perp, whole = agree(R, a, ref, FP64_TOL)
             else:
                 scale = np.abs(ref).max()
                 assert np.abs(R - ref).max() / scale < FP32_REL
-                assert np.abs(R - a).max() / scale < FP32_REL
+                ok, perp, whole = agree(R, a, ref, FP32_REL, relative=True)
+            # batched and alone: the same result up to the stopping error
+            # along the rank-mass direction (agreement.py)
+            assert ok, (perp, whole)
         # marks were consumed: a second batched call is a no-op
         before = [g.ranks() for g in handles]
         rc, stats = D.dfpr_update_many([g.h for g in handles])
