@@ -67,9 +67,10 @@ constexpr uint64_t kCursorMask = 0xFFFFFFFFull;
 constexpr uint64_t kInflightMask = 0xFFFFull;
 
 // Per-slot words of the barrier-based iteration (unsigned long long, one
-// 128-byte line per slot).  Wavefront w uses slot c = w % kClaimers: it
-// claims the items c + kClaimers * k from the slot's counter and adds its
-// statistics there, so no word is updated by every wavefront.
+// 128-byte line per slot).  Wavefront w uses slot c = w % nctr (nctr: at
+// most kClaimers, at most the grid's wavefronts): it claims the items
+// c + nctr * k from the slot's counter and adds its statistics there, so
+// no word is updated by every wavefront.
 constexpr int kClaimers = 16;
 constexpr int kClaimStride = 16;
 enum SlotWord {
@@ -367,12 +368,15 @@ struct MarkOut {
 // group were new (decided by the atomics).  The pre-checks skip the atomics
 // when the bits are already set: coherent (agent-scope) ones inside the
 // lock-free kernel, plain ones elsewhere, where a stale read only costs an
-// extra atomic.
+// extra atomic (bits only go from 0 to 1 within an update, so no read shows
+// a bit that is not set).  A vertex found affected needs nothing more: the
+// caller that set its bit lists its group.
 __device__ __forceinline__ MarkOut mark_affected(uint32_t *flags,
                                                  uint32_t *gflags, int32_t v,
                                                  bool coherent = true) {
   MarkOut o{false, false, v >> kGroupShift};
-  if (!(flag_byte(flags, v, coherent) & kVA)) o.vnew = !(flag_set(flags, v, kVA) & kVA);
+  if (flag_byte(flags, v, coherent) & kVA) return o;
+  o.vnew = !(flag_set(flags, v, kVA) & kVA);
   if (!(flag_byte(gflags, o.g, coherent) & kGA))
     o.gnew = !(flag_set(gflags, o.g, kGA) & kGA);
   return o;

@@ -1103,9 +1103,14 @@ __global__ void __launch_bounds__(256) k_sync_iter(RankArgs<T> A, const int32_t 
   const unsigned long long packed = A.sync_len[iter];
   const unsigned long long npieces = packed >> 32;
   const unsigned long long nitems = npieces + (packed & 0xFFFFFFFFull);
-  // claims are spread over kClaimers counters (item c + kClaimers * k from
-  // counter c): one hot counter serialised ~20K claims per iteration on
-  // the 2^22 R-MAT.  Every wavefront drains its own counter, so all items
+  // claims are spread over nctr counters, at most kClaimers and no more
+  // than the grid has wavefronts (item c + nctr * k from counter c): one
+  // hot counter serialised ~20K claims per iteration on the 2^22 R-MAT.
+  // (Blocks of consecutive items per counter, the counters of one XCD
+  // taking neighbouring blocks so that neighbouring steps share an L2,
+  // made the update slower on both the R-MAT and the road-like grid, and
+  // 1.3x slower on the 2^14 R-MAT.)  Every wavefront drains its own
+  // counter, so all items
   // are claimed unless wavefronts stop early (an injected stop fault); then
   // a wavefront that drained its own counter takes over the others in
   // turn, so the items behind a counter whose wavefronts stopped are still
@@ -1114,20 +1119,22 @@ __global__ void __launch_bounds__(256) k_sync_iter(RankArgs<T> A, const int32_t 
   // counter is a device-coherent access, and with the scan always on the
   // launches on the 2^22 R-MAT took 0.79 ms instead of 0.69 ms.
   const unsigned wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  const unsigned c = wave % kClaimers;
-  const unsigned scan = A.fault_stops ? (unsigned)kClaimers : 1u;
+  const unsigned nwaves = gridDim.x * (blockDim.x / kWave);
+  const unsigned nctr = nwaves < (unsigned)kClaimers ? nwaves : (unsigned)kClaimers;
+  const unsigned c = wave % nctr;
+  const unsigned scan = A.fault_stops ? nctr : 1u;
   bool stopped = false;
   for (unsigned k = 0; k < scan && !stopped; ++k) {
-    const unsigned cc = (c + k) % kClaimers;
+    const unsigned cc = (c + k) % nctr;
     unsigned long long *ctr = A.sync_grab + cc * kClaimStride;
     if (k > 0) {
       unsigned long long seen = 0;
       if (lane == 0) seen = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (cc + kClaimers * bcast0(seen) >= nitems) continue;
+      if (cc + nctr * bcast0(seen) >= nitems) continue;
     }
     while (true) {
       unsigned long long u = 0;
-      if (lane == 0) u = cc + kClaimers * atomicAdd(ctr, 1ull);
+      if (lane == 0) u = cc + nctr * atomicAdd(ctr, 1ull);
       u = bcast0(u);
       if (u >= nitems) break;
       if (u < npieces) {

@@ -612,6 +612,27 @@ def test_sync_claims_taken_over(D, O):
         assert rc == D.DFPR_OK and err64(g.ranks(), ref) < FP64_TOL
 
 
+@pytest.mark.parametrize("blocks,block", [(1, 64), (3, 128)])
+def test_sync_grid_smaller_than_claim_counters(D, O, blocks, block):
+    # fewer wavefronts (1 and 6) than claim counters, far fewer than an
+    # iteration's work items: every item is still claimed, static and DF
+    say("sync tiny grid", blocks, block)
+    n, s, d = inputs.rmat_small()
+    b = inputs.batches(n, s, d, 1, seed=1301, frac=1e-3)[0]
+    R0, _, _ = O.pagerank(n, s, d)
+    ns, nd, _, _ = O.apply_batch(n, s, d, b.del_src, b.del_dst, b.ins_src, b.ins_dst)
+    ref, _, _ = O.pagerank(n, ns, nd)
+    with graph(D, n, s, d, mode=D.DFPR_SYNC) as g:
+        g.set_params(grid_blocks=blocks, block_size=block)
+        rc, st = g.static()
+        assert rc == D.DFPR_OK and st.converged
+        assert err64(g.ranks(), R0) < FP64_TOL
+        g.apply(b)
+        rc, st = g.update()
+        assert rc == D.DFPR_OK and st.converged
+        assert err64(g.ranks(), ref) < FP64_TOL
+
+
 # --- Dynamic Traversal (Algorithms 7 and 8) ------------------------------------
 
 @pytest.mark.parametrize("case", ["sparse_rmat", "grid", "heavy_rows"])
