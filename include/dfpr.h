@@ -96,9 +96,11 @@ typedef struct {
                             large graphs)                                   */
   int32_t kahan_min_degree; /* fp32 ranks, barrier-based scheme: rows with
                                at least this in-degree accumulate in fp64,
-                               shorter rows in fp32 (default 64); the
-                               lock-free scheme accumulates every row in
-                               fp64                                         */
+                               shorter rows in fp32 (default 0: every row
+                               in fp64, which measured faster, as fp32 LDS
+                               atomic adds to one row stall the wavefront);
+                               the lock-free scheme accumulates every row
+                               in fp64                                      */
   int32_t split_min_degree; /* (default 2048) rows with at least this
                                in-degree are summed in pieces of 4096
                                in-edges by whole wavefronts (partial sums

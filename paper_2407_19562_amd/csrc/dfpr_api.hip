@@ -177,7 +177,7 @@ int dfpr_params_default(dfpr_params *p) {
   p->max_iters = 500;
   p->precision = 64;
   p->mode = DFPR_ASYNC;
-  p->kahan_min_degree = 64;
+  p->kahan_min_degree = 0;
   p->split_min_degree = 2048;
   p->chunk = 0;
   p->block_size = 0;

@@ -292,8 +292,22 @@ __device__ __forceinline__ void gather_flat(const RankArgs<T> &A, WaveLds<T> &L,
                                             const int64_t *off,
                                             const int32_t *deg, double *sum) {
   const int lane = lane_id();
+  // barrier-based scheme, fp32 ranks: rows of at least kahan_min in-edges
+  // sum in fp64, shorter ones in fp32; the choice rides in bit 62 of the
+  // row's offset in LDS (read there anyway) and in bit 8 of the owner, so
+  // no edge reads the row's length again
+  constexpr bool kMixed = sizeof(T) == 4 && !COH;
+  constexpr int64_t kWideBit = 1ll << 62;
   int32_t rank[kQ];
-  const int32_t total = flatten_nonempty(L, off, deg, rank);
+  int32_t total;
+  if constexpr (kMixed) {
+    int64_t offw[kQ];
+#pragma unroll
+    for (int k = 0; k < kQ; ++k) offw[k] = off[k] | (deg[k] >= A.kahan_min ? kWideBit : 0);
+    total = flatten_nonempty(L, offw, deg, rank);
+  } else {
+    total = flatten_nonempty(L, off, deg, rank);
+  }
   const bool bitmap = total <= kBitCap;
   int own[kUnroll];
   int32_t idx[kUnroll];
@@ -315,8 +329,14 @@ __device__ __forceinline__ void gather_flat(const RankArgs<T> &A, WaveLds<T> &L,
       } else {
         o = find_owner(L.pre, ec);
       }
-      idx[j] = A.in_adj[L.off[o] + (ec - L.pre[o])];
-      own[j] = e < total ? o : -1;
+      const int64_t ro = L.off[o];
+      if constexpr (kMixed) {
+        idx[j] = A.in_adj[(ro & (kWideBit - 1)) + (ec - L.pre[o])];
+        own[j] = e < total ? (o | (ro & kWideBit ? 0x100 : 0)) : -1;
+      } else {
+        idx[j] = A.in_adj[ro + (ec - L.pre[o])];
+        own[j] = e < total ? o : -1;
+      }
     }
   };
   if (total > 0) fetch(0);
@@ -333,18 +353,18 @@ __device__ __forceinline__ void gather_flat(const RankArgs<T> &A, WaveLds<T> &L,
 #pragma unroll
     for (int j = 0; j < kUnroll; ++j) {
       if (cur[j] < 0) continue;
-      if constexpr (sizeof(T) == 8 || COH) {
+      if constexpr (!kMixed) {
         // lock-free scheme, fp32 ranks: every row in fp64 as well.  fp32
         // atomics add in arrival order, so a row's rounded sum can differ
         // by ulps from one sweep to the next, and a rank that keeps moving
         // by two ulps never meets the stopping rule
         atomicAdd(&L.acc[cur[j]], (double)c[j]);
       } else {
-        const int32_t dlen = L.pre[cur[j] + 1] - L.pre[cur[j]];
-        if (dlen >= A.kahan_min)
-          atomicAdd(&L.acc[cur[j]], (double)c[j]);
+        const int r = cur[j] & 0xFF;
+        if (cur[j] & 0x100)
+          atomicAdd(&L.acc[r], (double)c[j]);
         else
-          atomicAdd(&L.accf[cur[j]], (float)c[j]);
+          atomicAdd(&L.accf[r], (float)c[j]);
       }
     }
   }

@@ -396,16 +396,20 @@ def test_graph_replay_matches_launches(D, O, kind):
         assert err64(Rr, ref) < FP64_TOL
 
 
-@pytest.mark.parametrize("mode", ["sync", "async"])
-def test_df_fp32_matches_oracle(D, O, mode):
-    say("df fp32", mode)
+@pytest.mark.parametrize("mode,kahan", [("sync", 0), ("sync", 8), ("sync", 1 << 30),
+                                        ("async", 0)])
+def test_df_fp32_matches_oracle(D, O, mode, kahan):
+    # kahan_min_degree: rows below it sum in fp32 (barrier-based scheme);
+    # 0, the default, sums every row in fp64; 8 splits the 2^14 R-MAT's
+    # rows between the two; 2^30 sums every row in fp32
+    say("df fp32", mode, kahan)
     n, s, d = inputs.rmat_small()
     R0, _, _ = O.pagerank(n, s, d)
     b = inputs.batches(n, s, d, 1, 1001, frac=1e-3)[0]
     ns, nd, res, _, _ = O.update(n, s, d, b, R0)
     ref, _, _ = O.pagerank(n, ns, nd)
     m = D.DFPR_SYNC if mode == "sync" else D.DFPR_ASYNC
-    with graph(D, n, s, d, mode=m, precision=32, renormalize=1) as g:
+    with graph(D, n, s, d, mode=m, precision=32, renormalize=1, kahan_min_degree=kahan) as g:
         g.set_ranks(R0)
         g.apply(b)
         rc, st = g.update()
