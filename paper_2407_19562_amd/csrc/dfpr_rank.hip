@@ -494,12 +494,16 @@ __device__ __forceinline__ void finish_rows(const RankArgs<T> &A, WaveLds<T> &L,
     oo[k] = 0;
     if (v[k] < 0) continue;
     const int32_t x = v[k];
+    // every per-vertex value in one round trip: the flag byte and the
+    // out-row offset are needed only if the vertex moved
     const double selfc = (double)ldc<T, COH>(A.Cr, x);
+    const T old = COH ? load_agent(A.Rr + x) : A.Rr[x];
+    const int32_t d = A.out_deg[x];
+    const uint32_t fb = MODE != kAll ? flag_byte(A.flags, x, COH) : 0u;
+    const int64_t xo = MODE != kAll ? A.out_off[x] : 0;
     const double r = A.base + A.alpha * (sum[k] + selfc);
     const T rT = (T)r;
-    const T old = COH ? load_agent(A.Rr + x) : A.Rr[x];
     const double dr = fabs((double)rT - (double)old);
-    const int32_t d = A.out_deg[x];
     const T cT = (T)(r / (double)(d + 1));
     if constexpr (COH) {
       store_agent(A.Rw + x, rT);
@@ -525,7 +529,7 @@ __device__ __forceinline__ void finish_rows(const RankArgs<T> &A, WaveLds<T> &L,
       if (dr > A.ftol) {
         // a vertex that already marked all its out-neighbours has nothing
         // left to mark: affected flags are never cleared within an update
-        if (!(flag_byte(A.flags, x, COH) & kEX)) {
+        if (!(fb & kEX)) {
           expand[k] = true;
           cnt.out_scanned += (unsigned long long)d;
           if (MODE == kSyncDF && d >= A.split_min) {
@@ -535,7 +539,7 @@ __device__ __forceinline__ void finish_rows(const RankArgs<T> &A, WaveLds<T> &L,
             A.xrow[j] = x;
           } else {
             od[k] = d;
-            oo[k] = A.out_off[x];
+            oo[k] = xo;
             any_expand = any_expand || d > 0;
           }
         }
@@ -569,11 +573,14 @@ __device__ __forceinline__ void process_step(const RankArgs<T> &A, WaveLds<T> &L
     off[k] = 0;
     deg[k] = 0;
     if (v[k] >= 0) {
+      // degree and offset in one round trip (the offset of a long row is
+      // read for nothing)
       const int32_t d = A.in_deg[v[k]];
+      const int64_t o = A.in_off[v[k]];
       if (d >= A.split_min) {
         v[k] = -1;
       } else {
-        off[k] = A.in_off[v[k]];
+        off[k] = o;
         deg[k] = d;
       }
     }
