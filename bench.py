@@ -59,7 +59,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat22",
                     choices=["rmat22", "rmat14", "sweep", "grid4096",
-                             "batched1024", "serving", "faults", "traversal", "vertices"])
+                             "batched1024", "serving", "faults", "traversal", "vertices",
+                             "ftol"])
     ap.add_argument("--frac", type=float, default=1e-3)
     ap.add_argument("--precision", type=int, default=64, choices=[32, 64])
     ap.add_argument("--mode", default="sync", choices=["async", "sync"])
@@ -538,6 +539,56 @@ def traversal(args, torch, dfpr, inputs):
             "results": out}
 
 
+FTOLS = (1e-8, 1e-9, 1e-10, 1e-11, 1e-13, 1e-15)
+
+
+def ftol_sweep(args, torch, dfpr, inputs):
+    """The frontier tolerance tau_f (Section 4.4, tau / 1000 by default)
+    against the work it causes and the error it leaves: the 2^22 R-MAT and
+    the road-like grid, one batch of 1e-4|E| from the static ranks, each
+    scheme, fp64; per tau_f the affected vertices, edges gathered, sweeps,
+    update time and L-infinity error against the oracle's fixed point of
+    the updated graph."""
+    out = {}
+    for name in ("rmat22", "grid4096"):
+        n, s, d, desc = load_workload(name)
+        ds, dd = torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda()
+        ov = overrides(args)
+        bs = inputs.batches(n, s, d, 1, seed=batch_seed(name, 1e-4) + 7, frac=1e-4)
+        dev = device_batches(torch, bs)
+        ref = None if args.no_oracle_error else oracle_ranks(n, *oracle_graph(n, s, d, [bs]))
+        for mode in ("sync", "async"):
+            g = dfpr.Graph(n, ds, dd, mode=MODES[mode], **ov)
+            g.static()
+            R0 = g.ranks()
+            g.close()
+            for ft in FTOLS:
+                g = dfpr.Graph(n, ds, dd, mode=MODES[mode], frontier_tol=ft, **ov)
+                g.set_ranks(R0)
+                torch.cuda.synchronize()
+                ts = time.perf_counter()
+                g.apply_batch(*dev[0])
+                rc, st = g.update()
+                ms = (time.perf_counter() - ts) * 1e3
+                if rc < 0:
+                    raise RuntimeError(f"update failed {rc}")
+                final = g.ranks()
+                g.close()
+                key = f"{name}_{mode}_ftol{ft:g}"
+                out[key] = {"ms": ms, "update_device_ms": st.ms, "sweeps": st.sweeps,
+                            "affected": st.affected, "edges_gathered": st.edges_gathered,
+                            "converged": bool(st.converged)}
+                if ref is not None:
+                    out[key]["error_vs_oracle"] = error_vs(final, ref, 64)
+                log(f"{key}: {out[key]}")
+    return {"metric": METRIC, "workload": "ftol", "unit": "ms",
+            "config": {"workload": "R-MAT 2^22 (seed 2) and 4096x4096 road-like grid (seed 3)",
+                       "batch": "1e-4*|E| (80/20), one batch from the static ranks",
+                       "sweep": "frontier tolerance " + ", ".join(f"{x:g}" for x in FTOLS) +
+                                " (tol 1e-10)"},
+            "results": out}
+
+
 def vertices(args, torch, dfpr, inputs):
     """Vertex insertion and removal on the 2^22 R-MAT (fp64, barrier-based
     DF): add k vertices with 16 in- and 16 out-edges each to random old
@@ -729,7 +780,7 @@ def main():
     torch.cuda.set_device(0)
     fn = {"rmat22": headline, "rmat14": headline, "sweep": sweep,
           "grid4096": grid, "batched1024": batched, "serving": serving,
-          "faults": faults, "traversal": traversal,
+          "faults": faults, "traversal": traversal, "ftol": ftol_sweep,
           "vertices": vertices}[args.workload]
     result = fn(args, torch, dfpr, inputs)
     print(json.dumps(result), flush=True)

@@ -278,6 +278,39 @@ def test_df_fp64_matches_oracle(D, O, mode, frac, kind, reorder):
         assert abs(st.affected - int(res.affected.sum())) <= max(3, res.affected.sum() // 1000)
 
 
+def test_frontier_tolerance_sweep(D, O):
+    # the frontier tolerance tau_f (Section 4.4) against the oracle's
+    # Algorithm 1 at the same tau_f: the barrier-based update affects the
+    # same vertices and ends at the same ranks for every tau_f; the error
+    # against the fixed point grows once tau_f nears tau, and at the paper's
+    # tau / 1000 both schemes meet the bar
+    say("frontier tolerance sweep")
+    n, s, d, R0 = base_graph(O, "rmat_small")
+    b = inputs.batches(n, s, d, 1, 1001, frac=1e-4)[0]
+    ns, nd, _, _ = O.apply_batch(n, s, d, b.del_src, b.del_dst, b.ins_src, b.ins_dst)
+    ref, _, _ = O.pagerank(n, ns, nd)
+    errs = {}
+    for ft in (1e-8, 1e-9, 1e-10, 1e-13, 0.0):
+        _, _, res, _, _ = O.update(n, s, d, b, R0, ftol=ft)
+        with graph(D, n, s, d, mode=D.DFPR_SYNC, frontier_tol=ft) as g:
+            g.set_ranks(R0)
+            g.apply(b)
+            rc, st = g.update()
+            assert rc == D.DFPR_OK and st.converged
+            R = g.ranks()
+        say("  tau_f", ft, "affected", st.affected, int(res.affected.sum()),
+            "err", err64(R, ref), err64(res.R, ref))
+        assert abs(st.affected - int(res.affected.sum())) <= max(3, res.affected.sum() // 1000)
+        assert err64(R, res.R) < FP64_TOL
+        errs[ft] = err64(R, ref)
+    assert errs[1e-8] > FP64_TOL >= errs[1e-13]
+    with graph(D, n, s, d, mode=D.DFPR_ASYNC) as g:
+        g.set_ranks(R0)
+        g.apply(b)
+        rc, st = g.update()
+        assert rc == D.DFPR_OK and err64(g.ranks(), ref) < FP64_TOL
+
+
 @pytest.mark.parametrize("kind", ["rmat_small", "heavy_rows"])
 @pytest.mark.parametrize("prec", [64, 32])
 def test_lock_free_stop_rules(D, O, kind, prec):

@@ -489,3 +489,27 @@ def test_add_then_remove_round_trip(oracle_lib):
     s2, d2, r2, _ = oracle_lib.remove_vertices_update(n + 7, s1, d1, 7, r1.R)
     assert r2.initial_marked == 0
     assert np.abs(r2.R - R0).max() < 1e-15
+
+
+def test_frontier_tolerance_trade_off(oracle_lib):
+    # Section 4.4: a smaller frontier tolerance affects more vertices and
+    # leaves a smaller error.  On the 2^14 R-MAT with a 1e-4|E| batch the
+    # affected set grows as tau_f falls and stops growing below tau / 10;
+    # at tau_f = 1e-8 the result misses the fp64 bar, at tau / 1000 it
+    # meets it, and tau_f = 0 (every change expands) affects a superset
+    n, s, d = inputs.rmat_small()
+    R0, _, _ = oracle_lib.pagerank(n, s, d)
+    b = inputs.batches(n, s, d, 1, 1001, frac=1e-4)[0]
+    ns, nd, _, _ = oracle_lib.apply_batch(n, s, d, b.del_src, b.del_dst, b.ins_src, b.ins_dst)
+    ref, _, _ = oracle_lib.pagerank(n, ns, nd)
+    prev_aff, affs, errs = None, {}, {}
+    for ft in (1e-8, 1e-9, 1e-10, 1e-11, 1e-13, 0.0):
+        _, _, res, _, _ = oracle_lib.update(n, s, d, b, R0, ftol=ft)
+        if prev_aff is not None:
+            assert np.all(res.affected[prev_aff])  # affected sets nest
+        prev_aff = res.affected
+        affs[ft] = int(res.affected.sum())
+        errs[ft] = float(np.abs(res.R - ref).max())
+    assert affs[1e-8] < affs[1e-9] < affs[1e-10] <= affs[1e-13] == affs[0.0]
+    assert errs[1e-8] > 1e-9 >= errs[1e-13]
+    assert errs[1e-8] > errs[1e-9] > errs[1e-10]
