@@ -43,6 +43,7 @@ constexpr int32_t kLongApply = 4096;  // row entries from which rows are
                                       // edited by more than one wavefront
 constexpr int kLongBlock = 1024;      // threads of a long-row deletion block
 constexpr int kKeyLds = 2048;         // segment keys staged in LDS
+constexpr int kDelPer = 8;            // row entries per thread and round of it
 
 inline int grid_for(int64_t work, int cu) {
   int64_t b = (work + 255) / 256;
@@ -244,15 +245,23 @@ __global__ void __launch_bounds__(kLongBlock) k_apply_delete_long(
     const uint32_t row = (uint32_t)(uk[a] >> 32);
     const int64_t off = A.off[row];
     const int32_t deg = A.deg[row];
+    // each thread takes kDelPer consecutive entries per round, so a row of
+    // 100,000 entries takes 13 rounds (each a memory round trip and a
+    // block scan) instead of 100
     int32_t w = 0;
-    for (int32_t t = 0; t < deg; t += blockDim.x) {
-      const int32_t idx = t + (int32_t)threadIdx.x;
-      int32_t x = -1;
-      bool keep = false;
-      if (idx < deg) {
-        x = A.adj[off + idx];
+    const int32_t step = (int32_t)blockDim.x * kDelPer;
+    for (int32_t t = 0; t < deg; t += step) {
+      const int32_t first = t + (int32_t)threadIdx.x * kDelPer;
+      int32_t xs[kDelPer];
+#pragma unroll
+      for (int i = 0; i < kDelPer; ++i) xs[i] = first + i < deg ? A.adj[off + first + i] : -1;
+      uint32_t keepm = 0;
+      int32_t cnt = 0;
+#pragma unroll
+      for (int i = 0; i < kDelPer; ++i) {
+        if (first + i >= deg) break;
         const unsigned long long key =
-            (unsigned long long)row << 32 | (unsigned long long)(uint32_t)x << 1;
+            (unsigned long long)row << 32 | (unsigned long long)(uint32_t)xs[i] << 1;
         int64_t k = -1;
         if (staged) {
           const int32_t q = find_key_lds(keys, (int32_t)nk, key);
@@ -260,14 +269,20 @@ __global__ void __launch_bounds__(kLongBlock) k_apply_delete_long(
         } else {
           k = find_key(uk, a, b, key);
         }
-        if (k >= 0) status[k] |= kApplied;
-        keep = k < 0;
+        if (k >= 0) {
+          status[k] |= kApplied;
+        } else {
+          keepm |= 1u << i;
+          ++cnt;
+        }
       }
       int32_t total = 0;
       // every entry of this round is read before the scan's barriers; the
-      // survivors land at or below their own positions
-      const int32_t pos = block_scan_excl(keep ? 1 : 0, part, &total);
-      if (keep) A.adj[off + w + pos] = x;
+      // survivors land, in order, at or below their own positions
+      int32_t pos = w + block_scan_excl(cnt, part, &total);
+#pragma unroll
+      for (int i = 0; i < kDelPer; ++i)
+        if (keepm & (1u << i)) A.adj[off + pos++] = xs[i];
       w += total;
     }
     if (threadIdx.x == 0) A.deg[row] = w;
@@ -295,13 +310,21 @@ __global__ void k_apply_insert(int64_t S, const int64_t *segstart,
       if (lane == 0) done[s] = 1;
       continue;
     }
-    for (int32_t t = 0; t < deg; t += kWave) {
-      const int32_t idx = t + lane;
-      if (idx < deg) {
-        const int32_t x = A.adj[off + idx];
+    // kDelPer row entries per lane in flight at once: the longest row
+    // (a hub's in-row of ~10^5 entries) bounds the kernel
+    for (int32_t t = 0; t < deg; t += kWave * kDelPer) {
+      int32_t xs[kDelPer];
+#pragma unroll
+      for (int i = 0; i < kDelPer; ++i) {
+        const int32_t idx = t + i * kWave + lane;
+        xs[i] = idx < deg ? A.adj[off + idx] : -1;
+      }
+#pragma unroll
+      for (int i = 0; i < kDelPer; ++i) {
+        if (t + i * kWave + lane >= deg) continue;
         const int64_t j = find_key(uk, a, b,
                                    (unsigned long long)row << 32 |
-                                       (unsigned long long)(uint32_t)x << 1 | 1ull);
+                                       (unsigned long long)(uint32_t)xs[i] << 1 | 1ull);
         if (j >= 0) status[j] |= kExists;
       }
     }
@@ -431,8 +454,19 @@ __global__ void k_mark_long(const int32_t *long_list, AdjView out, uint32_t *fla
     const int32_t u = long_list[j];
     const int64_t off = out.off[u];
     const int32_t deg = out.deg[u];
-    for (int32_t idx = threadIdx.x; idx < deg; idx += blockDim.x)
-      mark_plain(flags, gflags, out.adj[off + idx]);
+    // kDelPer entries per thread in flight at once: a row of 100,000
+    // entries is a few rounds of loads, not one per 1024 entries
+    for (int32_t t = threadIdx.x; t < deg; t += (int32_t)blockDim.x * kDelPer) {
+      int32_t v[kDelPer];
+#pragma unroll
+      for (int i = 0; i < kDelPer; ++i) {
+        const int32_t idx = t + i * (int32_t)blockDim.x;
+        v[i] = idx < deg ? out.adj[off + idx] : -1;
+      }
+#pragma unroll
+      for (int i = 0; i < kDelPer; ++i)
+        if (v[i] >= 0) mark_plain(flags, gflags, v[i]);
+    }
   }
 }
 
