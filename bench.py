@@ -680,7 +680,7 @@ def batched(args, torch, dfpr, inputs):
                 best, table = None, []
             # the one-by-one set keeps the library defaults, which suit
             # single small graphs
-            default = {"split_min_degree": 2048, "chunk": 0, "block_size": 0}
+            default = {"split_min_degree": 0, "chunk": 0, "block_size": 0}
             t_def = [t for t, c in table if c == default]
             t_best = min((t for t, _ in table), default=math.inf)
             if best is not None:

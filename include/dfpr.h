@@ -101,14 +101,15 @@ typedef struct {
                                atomic adds to one row stall the wavefront);
                                the lock-free scheme accumulates every row
                                in fp64                                      */
-  int32_t split_min_degree; /* (default 2048) rows with at least this
-                               in-degree are summed in pieces of 4096
-                               in-edges by whole wavefronts (partial sums
-                               added in piece order), the rest in
-                               edge-balanced steps of up to 256 rows; in
-                               the lock-free scheme a row's pieces are
-                               claimed like groups, and rows of 8192 or more
-                               in-edges always go in pieces there (a claim
+  int32_t split_min_degree; /* rows with at least this in-degree are
+                               summed in pieces of 4096 in-edges by whole
+                               wavefronts (partial sums added in piece
+                               order), the rest in edge-balanced steps of
+                               up to 256 rows; 0 (default): 2048 for the
+                               barrier-based scheme, 8192 for the lock-free
+                               one.  In the lock-free scheme a row's pieces
+                               are claimed like groups, and rows of 8192 or
+                               more in-edges always go in pieces (a claim
                                must stay short next to a sweep)            */
   int32_t chunk;         /* lock-free scheme: vertices per wavefront of a
                             claim, whole 256-vertex groups (chunk / 256, at

@@ -15,7 +15,8 @@ Spaces:
   async   one graph or many in one persistent launch (lock-free scheme):
           the vertex-to-wavefront mapping (split_min_degree: rows below it
           share a wavefront's 256-vertex step, rows at or above it get one
-          wavefront per 4096-edge piece), groups per claim (chunk / 256;
+          wavefront per 4096-edge piece; 0 = the library's choice), groups
+          per claim (chunk / 256;
           0 = the library's choice) and the workgroup size (0 = the
           library's choice).
 
@@ -43,7 +44,7 @@ SPACES = {
     "sync": [{"split_min_degree": s, "block_size": b}
              for s in (1024, 2048, 4096) for b in (128, 256)],
     "async": [{"split_min_degree": s, "chunk": c, "block_size": b}
-              for s in (512, 2048, 8192)
+              for s in (0, 512, 2048)
               for c in (0, 1024, 4096) for b in (0, 64, 128, 256)],
 }
 

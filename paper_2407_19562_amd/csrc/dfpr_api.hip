@@ -58,7 +58,7 @@ int check_params(const dfpr_params *p) {
   if (p->precision != 32 && p->precision != 64)
     return fail(DFPR_EINVAL, "precision must be 32 or 64");
   if (p->mode != DFPR_ASYNC && p->mode != DFPR_SYNC) return fail(DFPR_EINVAL, "bad mode");
-  if (p->split_min_degree < 1) return fail(DFPR_EINVAL, "split_min_degree must be >= 1");
+  if (p->split_min_degree < 0) return fail(DFPR_EINVAL, "split_min_degree must be >= 0");
   if (p->kahan_min_degree < 0) return fail(DFPR_EINVAL, "kahan_min_degree must be >= 0");
   if (p->chunk != 0 && (p->chunk < 64 || p->chunk % 64 || p->chunk > 4096))
     return fail(DFPR_EINVAL, "chunk must be 0 or a multiple of 64 in [64, 4096]");
@@ -178,7 +178,7 @@ int dfpr_params_default(dfpr_params *p) {
   p->precision = 64;
   p->mode = DFPR_ASYNC;
   p->kahan_min_degree = 0;
-  p->split_min_degree = 2048;
+  p->split_min_degree = 0;
   p->chunk = 0;
   p->block_size = 0;
   p->reorder = 2;

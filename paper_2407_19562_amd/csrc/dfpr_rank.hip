@@ -1622,6 +1622,29 @@ inline long long async_blocks(long long chunks, int cu_count, int waves_per_bloc
   return b > 0 ? b : 1;
 }
 
+// The lock-free scheme sums rows of kAsyncSplitMax in-edges or more in
+// pieces whatever split_min_degree says: a claim must stay short next to a
+// sweep, since a claim that outlives the sweep it began in computes from
+// values a sweep old (with pieces disabled, one wavefront summing a
+// 25,000-edge row ended the update 1.1e-9 from the fixed point).
+constexpr int32_t kAsyncSplitMax = 8192;
+// Default piece thresholds (split_min_degree 0): 2048 in-edges for the
+// barrier-based scheme (512 and 1024 slower, 4096 equal on the 2^22
+// R-MAT), kAsyncSplitMax for the lock-free one (2^22 R-MAT update 39.4 ms
+// with pieces from 2048 or 4096 in-edges, 35.2 ms from 8192: a piece's
+// partial sum is published and combined through memory, a row inside a
+// group part is summed in LDS).
+constexpr int32_t kSyncSplitDefault = 2048;
+
+inline int32_t sync_split(const dfpr_graph *g) {
+  return g->p.split_min_degree > 0 ? g->p.split_min_degree : kSyncSplitDefault;
+}
+
+inline int32_t async_split(const dfpr_graph *g) {
+  if (g->p.split_min_degree <= 0) return kAsyncSplitMax;
+  return g->p.split_min_degree < kAsyncSplitMax ? g->p.split_min_degree : kAsyncSplitMax;
+}
+
 template <typename T>
 RankArgs<T> make_args(dfpr_graph *g, int rd, int wr) {
   RankArgs<T> A;
@@ -1647,7 +1670,7 @@ RankArgs<T> make_args(dfpr_graph *g, int rd, int wr) {
   A.tol = g->p.tol;
   A.ftol = g->p.frontier_tol;
   A.wtol = g->p.lf_stop == DFPR_STOP_FRONTIER ? g->p.frontier_tol : g->p.tol;
-  A.split_min = g->p.split_min_degree;
+  A.split_min = sync_split(g);
   A.kahan_min = g->p.kahan_min_degree;
   A.chunk = effective_chunk(g);
   A.max_iters = g->p.max_iters;
@@ -2080,7 +2103,7 @@ void launch_items(dfpr_graph *g, bool all, bool reuse, hipStream_t s) {
   TileSum *sums = (TileSum *)g->tiles;
   TileSum *pre = sums + (nt + 1);
   const uint32_t *fl = g->flags;
-  const int32_t split = g->p.split_min_degree;
+  const int32_t split = sync_split(g);
   const int ru = all ? 0 : (reuse ? 1 : 0);
   const unsigned long long *sl = g->sync_grab;
   if (per == kTileLarge) {
@@ -2145,7 +2168,7 @@ int replay_graph(dfpr_graph *g, int mode, int blocks, size_t lds, F &launch_iter
                         g->out.deg, g->out.adj, g->in.deg};
   key = fnv1a(key, ptrs, sizeof(ptrs));
   const int64_t vals[] = {blocks, (int64_t)lds, block_for(g, kLaunchSync),
-                          g->p.split_min_degree, g->p.max_iters, g->n, g->cu_count,
+                          sync_split(g), g->p.max_iters, g->n, g->cu_count,
                           (int64_t)sizeof(T)};
   key = fnv1a(key, vals, sizeof(vals));
   double tol = g->p.tol;
@@ -2320,15 +2343,6 @@ int run_sync(dfpr_graph *g, int mode, dfpr_stats *st) {
 
 }  // namespace
 
-// The lock-free scheme sums rows of kAsyncSplitMax in-edges or more in
-// pieces whatever split_min_degree says: a claim must stay short next to a
-// sweep, since a claim that outlives the sweep it began in computes from
-// values a sweep old (with pieces disabled, one wavefront summing a
-// 25,000-edge row ended the update 1.1e-9 from the fixed point).
-constexpr int32_t kAsyncSplitMax = 8192;
-inline int32_t async_split(const dfpr_graph *g) {
-  return g->p.split_min_degree < kAsyncSplitMax ? g->p.split_min_degree : kAsyncSplitMax;
-}
 
 // Entries the lock-free worklist can hold at once: every piece, and every
 // group in its parts.  A group with s in-edges below the piece threshold
@@ -2346,10 +2360,11 @@ int64_t worklist_cap(const dfpr_graph *g) {
 // scheme's worklist holds every group and every piece.
 int ensure_split(dfpr_graph *g) {
   Split &S = g->split;
-  int64_t lcap = g->in.adj_cap / async_split(g) + 1;
+  const int32_t lmin = async_split(g) < sync_split(g) ? async_split(g) : sync_split(g);
+  int64_t lcap = g->in.adj_cap / lmin + 1;
   if (lcap > (int64_t)g->n + 1) lcap = (int64_t)g->n + 1;
   const int64_t pcap = g->in.adj_cap / kPiece + lcap + 1;
-  int64_t xcap = g->out.adj_cap / g->p.split_min_degree + 1;
+  int64_t xcap = g->out.adj_cap / sync_split(g) + 1;
   if (xcap > (int64_t)g->n + 1) xcap = (int64_t)g->n + 1;
   if (lcap > S.lcap || pcap > S.pcap || xcap > S.xcap) {
     DFPR_HIP(hipStreamSynchronize(g->stream));
@@ -2386,10 +2401,11 @@ int ensure_split(dfpr_graph *g) {
 // True when ensure_split would allocate nothing.
 bool split_ready(const dfpr_graph *g) {
   const Split &S = g->split;
-  int64_t lcap = g->in.adj_cap / async_split(g) + 1;
+  const int32_t lmin = async_split(g) < sync_split(g) ? async_split(g) : sync_split(g);
+  int64_t lcap = g->in.adj_cap / lmin + 1;
   if (lcap > (int64_t)g->n + 1) lcap = (int64_t)g->n + 1;
   const int64_t pcap = g->in.adj_cap / kPiece + lcap + 1;
-  int64_t xcap = g->out.adj_cap / g->p.split_min_degree + 1;
+  int64_t xcap = g->out.adj_cap / sync_split(g) + 1;
   if (xcap > (int64_t)g->n + 1) xcap = (int64_t)g->n + 1;
   return lcap <= S.lcap && pcap <= S.pcap && xcap <= S.xcap && worklist_cap(g) <= g->gwl_cap;
 }

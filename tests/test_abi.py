@@ -102,7 +102,7 @@ def test_null_graph_is_rejected(lib):
 
 @pytest.mark.parametrize("field,value", [
     ("chunk", 32), ("chunk", 100), ("chunk", 8192), ("block_size", 96),
-    ("block_size", 512), ("reorder", 3), ("split_min_degree", 0),
+    ("block_size", 512), ("reorder", 3), ("split_min_degree", -1),
     ("kahan_min_degree", -1), ("max_iters", 0), ("max_iters", 9000),
     ("precision", 16), ("grid_blocks", 1 << 20), ("timeout_ms", -5),
     ("graph_replay", 3)])
