@@ -1628,13 +1628,14 @@ inline long long async_blocks(long long chunks, int cu_count, int waves_per_bloc
 // values a sweep old (with pieces disabled, one wavefront summing a
 // 25,000-edge row ended the update 1.1e-9 from the fixed point).
 constexpr int32_t kAsyncSplitMax = 8192;
-// Default piece thresholds (split_min_degree 0): 2048 in-edges for the
-// barrier-based scheme (512 and 1024 slower, 4096 equal on the 2^22
-// R-MAT), kAsyncSplitMax for the lock-free one (2^22 R-MAT update 39.4 ms
-// with pieces from 2048 or 4096 in-edges, 35.2 ms from 8192: a piece's
-// partial sum is published and combined through memory, a row inside a
-// group part is summed in LDS).
-constexpr int32_t kSyncSplitDefault = 2048;
+// Default piece thresholds (split_min_degree 0), measured on the 2^22
+// R-MAT: barrier-based update 31.3 ms with pieces from 2048 or 4096
+// in-edges, 24.7 ms from anywhere in 6144..12288, 26.1 ms from 16384 (static
+// PageRank 41.4 -> 32.9 ms); lock-free update 39.4 ms from 2048 or 4096,
+// 35.2 ms from 8192, the most it allows.  A row of a few thousand in-edges
+// is summed faster inside a step (LDS accumulation) than as pieces whose
+// partial sums go through memory and a finishing wavefront.
+constexpr int32_t kSyncSplitDefault = 8192;
 
 inline int32_t sync_split(const dfpr_graph *g) {
   return g->p.split_min_degree > 0 ? g->p.split_min_degree : kSyncSplitDefault;
