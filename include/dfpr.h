@@ -105,9 +105,9 @@ typedef struct {
                                summed in pieces of 4096 in-edges by whole
                                wavefronts (partial sums added in piece
                                order), the rest in edge-balanced steps of
-                               up to 256 rows; 0 (default): 8192 (the
-                               library's choice for both schemes).  In the
-                               lock-free scheme a row's pieces
+                               up to 256 rows; 0 (default): 2048 for the
+                               barrier-based scheme, 8192 for the lock-free
+                               one.  In the lock-free scheme a row's pieces
                                are claimed like groups, and rows of 8192 or
                                more in-edges always go in pieces (a claim
                                must stay short next to a sweep)            */

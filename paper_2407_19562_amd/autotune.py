@@ -42,7 +42,7 @@ from . import dfpr, inputs
 
 SPACES = {
     "sync": [{"split_min_degree": s, "block_size": b}
-             for s in (0, 2048, 16384) for b in (0, 256)],
+             for s in (0, 8192, 16384) for b in (0, 256)],
     "async": [{"split_min_degree": s, "chunk": c, "block_size": b}
               for s in (0, 512, 2048)
               for c in (0, 1024, 4096) for b in (0, 64, 128, 256)],

@@ -168,6 +168,28 @@ constexpr size_t lds_bytes(int block_size) {
   return sizeof(WaveLds<T>) * (size_t)(block_size / kWave);
 }
 
+// s_waitcnt vmcnt(0) in the gfx9 encoding (expcnt and lgkmcnt at their
+// maxima): waits until the wavefront's global loads and stores complete.
+constexpr int kWaitVmcnt0 = 0x0F70;
+
+// Orders the calling wavefront's earlier global stores before its later
+// global accesses as every other wavefront of the device sees them, by
+// waiting until the stores have completed.  This suffices wherever the
+// values exchanged between wavefronts inside a launch are written and read
+// with device-scope atomic accesses (store_agent, load_agent, atomic RMWs):
+// those go to the device's coherence point past the XCD's L2, so a
+// completed store is visible to any later such load.  An agent-scope
+// release fence would also write back the XCD's L2 (buffer_wbl2) and an
+// acquire invalidate it (buffer_inv), which stalls every wavefront of the
+// XCD: per piece of a long row that had cost the barrier-based update on
+// the 2^22 R-MAT 31.3 against 22.5 ms, and per lock-free claim the grid
+// update 4.2 against 3.1 ms.
+__device__ __forceinline__ void stores_complete() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);  // no compiler reordering across
+  __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 // Orders LDS traffic of the lanes of one wavefront (no cross-wave sync).
 __device__ __forceinline__ void wave_lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -393,7 +415,7 @@ __device__ __forceinline__ void list_long_row(Ctl *ctl, int32_t *lrow, int32_t *
   store_agent(lcnt + j, 0);
   for (int32_t k = 0; k < np; ++k) store_agent(prow + p0 + k, (int32_t)j);
   // the row's table is in place before a claim can read one of its pieces
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  stores_complete();
   const unsigned long long pos = __hip_atomic_fetch_add(
       &ctl->gtail, (unsigned long long)np, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   for (int32_t k = 0; k < np; ++k) store_agent(gwl + pos + k, -(int32_t)(p0 + k) - 2);
@@ -648,12 +670,14 @@ __device__ void process_piece(const RankArgs<T> &A, WaveLds<T> &L, int32_t p,
     if (lane == 0) {
       store_agent(A.ppart + p, part);
       if (COH) store_agent(A.ptag + p, A.epoch);
-      const int32_t before = __hip_atomic_fetch_add(A.lcnt + j, 1, __ATOMIC_ACQ_REL,
+      // the partial sum (and tag) complete before the count that publishes
+      // them; the finishing wavefront reads them with device-scope loads
+      stores_complete();
+      const int32_t before = __hip_atomic_fetch_add(A.lcnt + j, 1, __ATOMIC_RELAXED,
                                                     __HIP_MEMORY_SCOPE_AGENT);
       last = COH ? (before + 1) % np == 0 : before == np - 1;
     }
     if (!__builtin_amdgcn_readfirstlane(last)) return;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if constexpr (COH) {
       bool have = true;
       for (int32_t k = lane; k < np; k += kWave)
@@ -791,7 +815,7 @@ __device__ __forceinline__ void release_mark(const RankArgs<T> &A, WaveSched &ws
   if (ws.moved)
     publish(A, ws, (long long)((load_agent(&A.ctl->state) >> kSweepShift) & kSweepMask));
   // the watermark update is performed before the in-flight mark drops
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  stores_complete();
   __hip_atomic_fetch_sub(&A.ctl->state, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   ws.held = false;
   ws.moved = false;
@@ -993,7 +1017,7 @@ __device__ int df_async_step(const RankArgs<T> &A, WaveLds<T> &L, Counters &cnt,
   // every store of this claim (ranks, contributions, flags, worklist
   // entries), by every wavefront, is performed before the workgroup's next
   // operation on the scheduling word, which gives its mark back
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  stores_complete();
   ws.moved = __syncthreads_or(moved ? 1 : 0) != 0;
   return kWorked;
 }
@@ -1629,13 +1653,13 @@ inline long long async_blocks(long long chunks, int cu_count, int waves_per_bloc
 // 25,000-edge row ended the update 1.1e-9 from the fixed point).
 constexpr int32_t kAsyncSplitMax = 8192;
 // Default piece thresholds (split_min_degree 0), measured on the 2^22
-// R-MAT: barrier-based update 31.3 ms with pieces from 2048 or 4096
-// in-edges, 24.7 ms from anywhere in 6144..12288, 26.1 ms from 16384 (static
-// PageRank 41.4 -> 32.9 ms); lock-free update 39.4 ms from 2048 or 4096,
-// 35.2 ms from 8192, the most it allows.  A row of a few thousand in-edges
-// is summed faster inside a step (LDS accumulation) than as pieces whose
-// partial sums go through memory and a finishing wavefront.
-constexpr int32_t kSyncSplitDefault = 8192;
+// R-MAT.  Barrier-based: update 22.5 ms with pieces from 2048 or 4096
+// in-edges, 22.7 ms from 8192, 26.3 ms from 16384.  Lock-free: 35.2 ms from
+// 2048 or 4096, 32.5 ms from 8192, the most it allows.  (While finishing a
+// row took acquire-release ordering, whose cache maintenance stalls a
+// whole XCD, each piece cost so much that 6144..12288 was the barrier-based
+// optimum at 24.7 ms, and 2048 gave 31.3 ms.)
+constexpr int32_t kSyncSplitDefault = 2048;
 
 inline int32_t sync_split(const dfpr_graph *g) {
   return g->p.split_min_degree > 0 ? g->p.split_min_degree : kSyncSplitDefault;

@@ -1,7 +1,7 @@
 """Parity at full size, in the launch configurations bench.py times: the
 2^22-vertex R-MAT with 67,108,864 edges (barrier-based DF in fp64 and fp32,
 lock-free DF in fp64; default parameters: degree-sorted order for the
-barrier-based scheme, 12 wavefronts per CU, pieces from in-degree 8192,
+barrier-based scheme, 12 wavefronts per CU, pieces from in-degree 2048,
 1024-vertex tiles) and the 4096 x 4096 road-like grid (barrier-based and
 lock-free).  Every vertex is compared with the oracle:
   * the GPU's static ranks with the oracle's fixed point of G^0;
