@@ -115,14 +115,15 @@ typedef struct {
                             claim, whole 256-vertex groups (chunk / 256, at
                             least one); a multiple of 64 in [64, 4096], or
                             0 (default): one group per 1024 groups of the
-                            graph, 1..16, and 16 groups in the batched
+                            graph, 1..16, and 4 groups in the batched
                             launch.  A claim is made by a whole workgroup,
                             for all its wavefronts                         */
   int32_t block_size;    /* threads per workgroup of the rank kernel: 64,
                             128, 192 or 256, or 0 (default): 128 for the
                             barrier-based scheme, 256 for the lock-free
-                            scheme on one graph, 64 for the batched launch
-                            (dfpr_update_many takes the first graph's)     */
+                            scheme on one graph, 128 for the batched
+                            launch (dfpr_update_many takes the first
+                            graph's)                                        */
   int32_t reorder;       /* internal vertex order, fixed at creation:
                             0 keep the caller's ids; 1 sort by decreasing
                             out-degree, so the contributions read most often

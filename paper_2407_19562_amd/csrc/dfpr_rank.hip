@@ -1596,12 +1596,13 @@ enum LaunchKind { kLaunchSync = 0, kLaunchAsync = 1, kLaunchMany = 2 };
 // next to the work of a small graph's sweep, and too few per sweep leave
 // the device idle on a small one: the 2^14 R-MAT ran 10x slower with 16
 // groups per wavefront than with one, the 2^22 R-MAT and the 4096 x 4096
-// grid fastest with 16, which 32 made slower again).  Batched launch: 16
-// groups, as the many graphs keep the device busy (measured 1.8x faster
-// than one group per wavefront over 1024 graphs of 1e3..1e6 edges).
+// grid fastest with 16, which 32 made slower again).  Batched launch: 4
+// groups, as the many graphs keep the device busy (over 1024 graphs of
+// 1e3..1e6 edges, 1.8x faster than one group per wavefront, and 9-13%
+// faster than 16).
 inline int effective_chunk(const dfpr_graph *g, int kind = kLaunchAsync) {
   if (g->p.chunk > 0) return g->p.chunk;
-  if (kind == kLaunchMany) return 16 * kGroup;
+  if (kind == kLaunchMany) return 4 * kGroup;
   int per = g->ngroups / 1024;
   per = per < 1 ? 1 : (per > 16 ? 16 : per);
   return per * kGroup;
@@ -1611,11 +1612,11 @@ inline int effective_chunk(const dfpr_graph *g, int kind = kLaunchAsync) {
 // by default 128 for the barrier-based scheme (256 was as fast on the large
 // graphs and 9% slower on the 2^14 R-MAT), 256 for the lock-free scheme on
 // one graph (a claim serves four wavefronts: the grid update took 4.4 ms
-// against 5.0 ms with 128), 64 for the batched launch (its autotuned
-// choice with 16-group claims).
+// against 5.0 ms with 128), 128 for the batched launch (its autotuned
+// choice with 4-group claims in both precisions).
 inline int block_for(const dfpr_graph *g, int kind) {
   if (g->p.block_size > 0) return g->p.block_size;
-  return kind == kLaunchSync ? 128 : (kind == kLaunchAsync ? 256 : 64);
+  return kind == kLaunchSync ? 128 : (kind == kLaunchAsync ? 256 : 128);
 }
 
 // Lock-free grid: enough workgroups that each takes about kChunksPerWave
