@@ -182,7 +182,7 @@ constexpr int kWaitVmcnt0 = 0x0F70;
 // release fence would also write back the XCD's L2 (buffer_wbl2) and an
 // acquire invalidate it (buffer_inv), which stalls every wavefront of the
 // XCD: per piece of a long row that had cost the barrier-based update on
-// the 2^22 R-MAT 31.3 against 22.5 ms, and per lock-free claim the grid
+// the 2^22 R-MAT 31.3 against 21.9 ms, and per lock-free claim the grid
 // update 4.2 against 3.1 ms.
 __device__ __forceinline__ void stores_complete() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);  // no compiler reordering across
@@ -726,8 +726,8 @@ __device__ __forceinline__ void flush_counters(Ctl *ctl, Counters &c) {
 // a rank change above the watermark tolerance wtol (the iteration
 // tolerance for DF updates, or the frontier tolerance) or met an entry it
 // could not finish raises change_sweep to the sweep index current when it
-// is published (after a release fence, and before the claim's in-flight
-// mark drops).  Sweep S may end the launch only when no claim is held and
+// is published (after the claim's stores completed, and before its
+// in-flight mark drops).  Sweep S may end the launch only when no claim is held and
 // change_sweep < S: then every worklist entry was processed during S and
 // no rank moved by more than wtol, so every R_C is 0.  Otherwise the next
 // sweep starts as soon as a claim completed during S has seen a change,
