@@ -379,20 +379,24 @@ def test_split_rows_match_oracle(D, O, split, prec, mode):
 
 def test_sync_update_is_deterministic(D, O):
     # piece sums are added in piece order and every step row is summed by
-    # one wavefront, so repeated runs give the same bits
+    # one wavefront, so repeated runs give the same bits; with pieces from
+    # in-degree 64 every iteration publishes thousands of partial sums
+    # through device-scope stores and counts (a partial read before it
+    # landed would change the bits)
     say("determinism")
     n, s, d = inputs.heavy_rows()
     R0, _, _ = O.pagerank(n, s, d)
     b = inputs.batches(n, s, d, 1, 78, frac=1e-2)[0]
     out = []
-    for _ in range(2):
+    for _ in range(4):
         with graph(D, n, s, d, mode=D.DFPR_SYNC, split_min_degree=64) as g:
             g.set_ranks(R0)
             g.apply(b)
             rc, st = g.update()
             assert rc == D.DFPR_OK
             out.append(g.ranks())
-    assert np.array_equal(out[0], out[1])
+    for r in out[1:]:
+        assert np.array_equal(out[0], r)
 
 
 @pytest.mark.parametrize("kind", ["rmat_small", "heavy_rows"])
