@@ -352,7 +352,16 @@ __global__ void k_apply_insert(int64_t S, const int64_t *segstart,
         if (lane == 0) atomicOr(overflow, 1);
         continue;  // left pending; the host grows the array and re-runs
       }
-      for (int32_t t = lane; t < deg; t += kWave) A.adj[p + t] = A.adj[off + t];
+      // the row moves to its new slot with kDelPer loads in flight per lane
+      for (int32_t t = lane; t < deg; t += kWave * kDelPer) {
+        int32_t x[kDelPer];
+#pragma unroll
+        for (int i = 0; i < kDelPer; ++i)
+          x[i] = t + i * kWave < deg ? A.adj[off + t + i * kWave] : 0;
+#pragma unroll
+        for (int i = 0; i < kDelPer; ++i)
+          if (t + i * kWave < deg) A.adj[p + t + i * kWave] = x[i];
+      }
       off = (int64_t)p;
       if (lane == 0) {
         A.off[row] = off;
@@ -636,7 +645,7 @@ int apply_batch(dfpr_graph *g, int64_t nd, const int32_t *ds,
       if (rc2) return rc2;
       if (attempt == 15) return fail(DFPR_ENOMEM, "adjacency growth did not converge");
     }
-    k_count_applied<<<grid_for(U[dir], cu), 256, 0, s>>>(
+    k_count_applied<<<grid_for(U[dir], cu) < 64 ? grid_for(U[dir], cu) : 64, 256, 0, s>>>(
         U[dir], uk[dir], st[dir],
         dir == 0 ? &g->ctl->del_applied : &g->ctl->del_applied_in,
         dir == 0 ? &g->ctl->ins_applied : &g->ctl->ins_applied_in);
@@ -665,7 +674,8 @@ int apply_batch(dfpr_graph *g, int64_t nd, const int32_t *ds,
     // the count covers every batch applied since the last update
     const int64_t words = ((int64_t)g->n + 3) / 4;
     DFPR_HIP(hipMemsetAsync(&g->ctl->marked, 0, sizeof(long long), s));
-    k_count_marked<<<grid_for(words, cu), 256, 0, s>>>(g->flags, words, g->ctl);
+    // one workgroup per CU: each adds its count with one atomic on one word
+    k_count_marked<<<cu > 0 ? cu : 1, 256, 0, s>>>(g->flags, words, g->ctl);
     DFPR_HIP(hipGetLastError());
   }
   DFPR_HIP(hipMemcpyAsync(g->h_ctl, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
