@@ -107,17 +107,20 @@ typedef struct {
                                order), the rest in edge-balanced steps of
                                up to 256 rows; 0 (default): 2048 for the
                                barrier-based scheme, 8192 for the lock-free
-                               one.  In the lock-free scheme a row's pieces
-                               are claimed like groups, and rows of 8192 or
-                               more in-edges always go in pieces (a claim
-                               must stay short next to a sweep)            */
+                               one (512 on a graph in degree-sorted order,
+                               see reorder).  In the lock-free scheme a
+                               row's pieces are claimed like groups, and
+                               rows of 8192 or more in-edges always go in
+                               pieces (a claim must stay short next to a
+                               sweep)                                       */
   int32_t chunk;         /* lock-free scheme: vertices per wavefront of a
                             claim, whole 256-vertex groups (chunk / 256, at
                             least one); a multiple of 64 in [64, 4096], or
                             0 (default): one group per 1024 groups of the
-                            graph, 1..16, and 4 groups in the batched
-                            launch.  A claim is made by a whole workgroup,
-                            for all its wavefronts                         */
+                            graph, 1..16 (1..4 on a graph in degree-sorted
+                            order), and 4 groups in the batched launch.  A
+                            claim is made by a whole workgroup, for all its
+                            wavefronts                                     */
   int32_t block_size;    /* threads per workgroup of the rank kernel: 64,
                             128, 192 or 256, or 0 (default): 128 for the
                             barrier-based scheme, 256 for the lock-free
@@ -128,10 +131,11 @@ typedef struct {
                             0 keep the caller's ids; 1 sort by decreasing
                             out-degree, so the contributions read most often
                             share cache lines; 2 (default) sort when the
-                            graph is large (n >= 2^20), its out-degree
-                            skewed (max >= 8 x mean) and the mode at
-                            creation is DFPR_SYNC.  Ids at the ABI are
-                            always the caller's.                           */
+                            graph is large (n >= 2^20) and its out-degree
+                            skewed (max >= 8 x mean).  On a sorted graph
+                            the lock-free scheme lists its groups
+                            interleaved, so that its claims stay even.
+                            Ids at the ABI are always the caller's.        */
   int32_t renormalize;   /* fp32: rescale ranks to sum 1 (fp64 sum) after
                             each update                                     */
   int32_t timeout_ms;    /* watchdog for the persistent kernel (0: none)    */

@@ -163,13 +163,11 @@ int build_graph(dfpr_graph *g, int64_t m, const int32_t *src,
     int32_t maxdeg = 0;
     for (int32_t x : hc) maxdeg = x > maxdeg ? x : maxdeg;
     const double mean = (double)m / (double)n;
-    // automatic: large, skewed graphs under the barrier-based scheme.  The
-    // lock-free scheme keeps the caller's order: with the sorted order its
-    // claims of whole groups were unequal (the first groups hold the
-    // heaviest rows) and its 2^22 R-MAT update ran 1.4x slower, although
-    // more of its contribution reads hit in L2
-    const bool autosort = (double)maxdeg >= 8.0 * mean && n >= (1 << 20) &&
-                          g->p.mode == DFPR_SYNC;
+    // automatic: large, skewed graphs, in either scheme (the lock-free
+    // scheme lists the groups of a sorted graph interleaved, with pieces
+    // from a lower in-degree and smaller claims, so that its claims stay
+    // even although the first groups hold the heaviest rows)
+    const bool autosort = (double)maxdeg >= 8.0 * mean && n >= (1 << 20);
     if (g->p.reorder == 1 || (g->p.reorder == 2 && autosort)) {
       if ((rc = scratch_get(g, 0, (size_t)n * 8, &keys_a))) return rc;
       if ((rc = scratch_get(g, 1, (size_t)n * 8, &keys_b))) return rc;

@@ -88,6 +88,8 @@ struct RankArgs {
   int32_t nfaults;
   int32_t fault_stops;           // some entry of faults stops its workgroups
   uint32_t ticks_per_us;         // wall-clock ticks per microsecond
+  int32_t group_stripes;         // lock-free: interleaved runs of the group
+                                 // worklist (list_groups)
 };
 
 // Injected fault of the calling workgroup, taken after each completed claim
@@ -1581,15 +1583,18 @@ inline int grid_for(int64_t work, int cu) {
   return (int)(b < 1 ? 1 : b);
 }
 
-// Lock-free scheme: vertices per wavefront of a claim (whole 256-vertex
-// groups; a workgroup claims that many for each of its wavefronts).  chunk
-// 0 picks one group per 2048 groups of the graph, between 1 and 8: on the
-// 2^22 R-MAT (16384 groups) claims of 16 groups for a two-wavefront
-// workgroup ran 1.6x faster than claims of 4 by single wavefronts, which
-// had run 2.5x faster than claims of one (every claim is an atomic on the
-// one scheduling word, and idle workgroups poll it).
 // Which launch a default launch parameter is chosen for.
 enum LaunchKind { kLaunchSync = 0, kLaunchAsync = 1, kLaunchMany = 2 };
+
+// The graph's internal order is by decreasing out-degree (reorder at
+// creation): its heaviest rows sit together in the first groups.
+inline bool degree_sorted(const dfpr_graph *g) { return g->int2ext != nullptr; }
+
+// Interleaved runs of the lock-free group worklist on a degree-sorted graph
+// (list_groups).  In id order its heaviest groups come first, and the
+// cursor ran through the light tail while claims on the heavy head were
+// still running: the 2^22 R-MAT update took 95 sweeps instead of 41.
+constexpr int32_t kGroupStripes = 64;
 
 // Vertices per wavefront of a lock-free claim.  Default, one graph: one
 // 256-vertex group per 1024 groups of the graph, 1..16 (claims are costly
@@ -1603,8 +1608,12 @@ enum LaunchKind { kLaunchSync = 0, kLaunchAsync = 1, kLaunchMany = 2 };
 inline int effective_chunk(const dfpr_graph *g, int kind = kLaunchAsync) {
   if (g->p.chunk > 0) return g->p.chunk;
   if (kind == kLaunchMany) return 4 * kGroup;
+  // a degree-sorted graph's heavy groups would make 16-group claims longer
+  // than a sweep: at most 4 there (2^22 R-MAT, sorted: 30.1 ms per update
+  // with 4-group claims against 48.7 ms with 16, pieces from 2048 in-edges)
+  const int most = degree_sorted(g) ? 4 : 16;
   int per = g->ngroups / 1024;
-  per = per < 1 ? 1 : (per > 16 ? 16 : per);
+  per = per < 1 ? 1 : (per > most ? most : per);
   return per * kGroup;
 }
 
@@ -1661,13 +1670,19 @@ constexpr int32_t kAsyncSplitMax = 8192;
 // whole XCD, each piece cost so much that 6144..12288 was the barrier-based
 // optimum at 24.7 ms, and 2048 gave 31.3 ms.)
 constexpr int32_t kSyncSplitDefault = 2048;
+// Lock-free default on a degree-sorted graph, where the rows just below the
+// threshold sit together in the first groups: 2^22 R-MAT update 23.7 ms
+// with pieces from 512 in-edges, 24.5 ms from 1024, 30.1 ms from 2048 (all
+// with 4-group claims); 2^20 R-MAT of average degree 4: 5.2 ms from 512,
+// 4.7 ms from 1024.
+constexpr int32_t kAsyncSplitSorted = 512;
 
 inline int32_t sync_split(const dfpr_graph *g) {
   return g->p.split_min_degree > 0 ? g->p.split_min_degree : kSyncSplitDefault;
 }
 
 inline int32_t async_split(const dfpr_graph *g) {
-  if (g->p.split_min_degree <= 0) return kAsyncSplitMax;
+  if (g->p.split_min_degree <= 0) return degree_sorted(g) ? kAsyncSplitSorted : kAsyncSplitMax;
   return g->p.split_min_degree < kAsyncSplitMax ? g->p.split_min_degree : kAsyncSplitMax;
 }
 
@@ -1718,6 +1733,7 @@ RankArgs<T> make_args(dfpr_graph *g, int rd, int wr) {
   A.nfaults = g->nfaults;
   A.fault_stops = g->nfaults > 0 ? g->fault_stops : 0;
   A.ticks_per_us = (uint32_t)(g->wallclock_khz / 1000 > 0 ? g->wallclock_khz / 1000 : 1);
+  A.group_stripes = degree_sorted(g) ? kGroupStripes : 1;
   return A;
 }
 
@@ -1954,17 +1970,23 @@ __global__ void __launch_bounds__(256) k_tile_emit(const uint32_t *flags,
 }
 
 // Group worklist of the lock-free scheme from the listed flags: one
-// 256-thread workgroup per graph compacts the graph's group flags in id
-// order into gwl, each listed group as its parts (log2 in the group byte),
-// after the entries already there (the pieces of the long rows,
-// k_list_long), and sets gtail.
+// 256-thread workgroup per graph compacts the graph's group flags into gwl,
+// each listed group as its parts (log2 in the group byte), after the
+// entries already there (the pieces of the long rows, k_list_long), and
+// sets gtail.  The groups go in id order (stripes 1), or interleaved from
+// `stripes` equal runs of ids: position i takes group (i mod stripes) *
+// rows + i / stripes, so neighbouring entries come from far-apart runs.
 __device__ __forceinline__ void list_groups(const uint8_t *gflags, int32_t ngroups,
-                                            int32_t *gwl, unsigned long long *gtail) {
+                                            int32_t *gwl, unsigned long long *gtail,
+                                            int32_t stripes) {
   __shared__ int32_t lds4[4];
   int32_t base = (int32_t)*gtail;
-  for (int32_t g0 = 0; g0 < ngroups; g0 += kRows) {
-    const int32_t gi = g0 + (int32_t)threadIdx.x;
-    const uint32_t b = gi < ngroups ? gflags[gi] : 0u;
+  const int32_t rows = (ngroups + stripes - 1) / stripes;
+  const int32_t padded = rows * stripes;
+  for (int32_t g0 = 0; g0 < padded; g0 += kRows) {
+    const int32_t i = g0 + (int32_t)threadIdx.x;
+    const int32_t gi = (i % stripes) * rows + i / stripes;
+    const uint32_t b = i < padded && gi < ngroups ? gflags[gi] : 0u;
     const bool sel = (b & kGA) != 0;
     const int32_t l = (int32_t)((b >> kGPartShift) & 7u);
     const int32_t cnt = sel ? (1 << l) : 0;
@@ -2062,8 +2084,8 @@ __global__ void k_zero_lcnt(int32_t *lcnt, const Ctl *ctl) {
 }
 
 __global__ void __launch_bounds__(256) k_list_groups(const uint32_t *gflags, int32_t ngroups,
-                                                     int32_t *gwl, Ctl *ctl) {
-  list_groups(reinterpret_cast<const uint8_t *>(gflags), ngroups, gwl, &ctl->gtail);
+                                                     int32_t *gwl, Ctl *ctl, int32_t stripes) {
+  list_groups(reinterpret_cast<const uint8_t *>(gflags), ngroups, gwl, &ctl->gtail, stripes);
 }
 
 template <typename T>
@@ -2071,7 +2093,7 @@ __global__ void __launch_bounds__(256) k_list_groups_many(const RankArgs<T> *des
   for (int i = blockIdx.x; i < count; i += gridDim.x) {
     const RankArgs<T> &A = descs[i];
     list_groups(reinterpret_cast<const uint8_t *>(A.gflags), (A.n + kGroup - 1) / kGroup,
-                A.gwl, &A.ctl->gtail);
+                A.gwl, &A.ctl->gtail, A.group_stripes);
     __syncthreads();
   }
 }
@@ -2478,7 +2500,8 @@ int run_async(dfpr_graph *g, dfpr_stats *st, bool all = false) {
       g->gflags, g->in.deg, g->n, g->ngroups, async_split(g));
   k_list_long<<<grid_for(g->n, g->cu_count), 256, 0, s>>>(
       g->flags, g->in.deg, g->n, async_split(g), g->ctl, g->split, g->gwl);
-  k_list_groups<<<1, 256, 0, s>>>(g->gflags, g->ngroups, g->gwl, g->ctl);
+  k_list_groups<<<1, 256, 0, s>>>(g->gflags, g->ngroups, g->gwl, g->ctl,
+                                  degree_sorted(g) ? kGroupStripes : 1);
   DFPR_HIP(hipGetLastError());
   RankArgs<T> A = make_args<T>(g, g->cur, g->cur);
   A.split_min = async_split(g);

@@ -248,7 +248,8 @@ def base_graph(O, kind):
 
 
 # rmat_mid (2^20 vertices) takes the large-graph paths: 1024-vertex tiles,
-# and with reorder 2 and the barrier-based scheme the degree-sorted order
+# and with reorder 2 the degree-sorted order (in the lock-free scheme also
+# the interleaved group worklist, pieces from 512 in-edges and 4-group claims)
 @pytest.mark.parametrize("kind,reorder", [("rmat_small", 0), ("rmat_small", 1),
                                           ("heavy_rows", 0), ("rmat_mid", 2)])
 @pytest.mark.parametrize("mode", ["sync", "async"])
