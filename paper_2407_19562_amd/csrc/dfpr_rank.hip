@@ -1500,13 +1500,20 @@ __global__ void k_sum(int32_t n, const T *R, double *out) {
   if (lane_id() == 0) atomicAdd(out, s);
 }
 
+// Renormalisation of fp32 ranks: adds (1 - sum) / n to every rank, so that
+// they sum to 1, and recomputes the contributions.  The missing mass is
+// mostly the update's own truncation (every affected vertex within tau of
+// the fixed point, errors of one sign), so a uniform shift keeps each rank
+// within that error; scaling by 1 / sum would move the largest ranks by
+// R_v * (sum - 1) instead (2^22 R-MAT, lock-free fp32: the top rank moved by
+// 1.8e-9, 3e-6 of its value).
 template <typename T>
-__global__ void k_scale(int32_t n, const int32_t *out_deg, const double *sum,
+__global__ void k_shift(int32_t n, const int32_t *out_deg, const double *sum,
                         T *R, T *C) {
-  const double f = 1.0 / *sum;
+  const double d = (1.0 - *sum) / (double)n;
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
        v += (int64_t)gridDim.x * blockDim.x) {
-    const double r = (double)R[v] * f;
+    const double r = (double)R[v] + d;
     R[v] = (T)r;
     C[v] = (T)(r / (double)(out_deg[v] + 1));
   }
@@ -2557,7 +2564,7 @@ int renormalize(dfpr_graph *g) {
   DFPR_HIP(hipMemsetAsync(&g->ctl->sum, 0, sizeof(double), s));
   k_sum<T><<<grid_for(g->n, g->cu_count), 256, 0, s>>>(g->n, (const T *)g->R[g->cur],
                                                        &g->ctl->sum);
-  k_scale<T><<<grid_for(g->n, g->cu_count), 256, 0, s>>>(
+  k_shift<T><<<grid_for(g->n, g->cu_count), 256, 0, s>>>(
       g->n, g->out.deg, &g->ctl->sum, (T *)g->R[g->cur], (T *)g->C[g->cur]);
   DFPR_HIP(hipGetLastError());
   return DFPR_OK;

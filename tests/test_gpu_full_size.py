@@ -55,6 +55,7 @@ CASES = [  # graph, scheme, precision, batch fraction, batch seed (as bench.py)
     ("rmat22", "sync", 64, 1e-3, 2020),
     ("rmat22", "sync", 32, 1e-3, 2020),
     ("rmat22", "async", 64, 1e-3, 2020),
+    ("rmat22", "async", 32, 1e-3, 2020),
     ("grid4096", "sync", 64, 1e-4, 3000),
     ("grid4096", "async", 64, 1e-4, 3000),
 ]
