@@ -136,8 +136,9 @@ typedef struct {
                             the lock-free scheme lists its groups
                             interleaved, so that its claims stay even.
                             Ids at the ABI are always the caller's.        */
-  int32_t renormalize;   /* fp32: after each update shift every rank by
-                            (1 - sum) / n (fp64 sum), so the ranks sum to 1 */
+  int32_t renormalize;   /* fp32: after each update rescale the ranks to
+                            sum 1 (fp64 sum) when they miss it by more than
+                            n * tol, the update's own truncation          */
   int32_t timeout_ms;    /* watchdog for the persistent kernel (0: none)    */
   int32_t grid_blocks;   /* workgroups of the rank kernels; 0 = automatic:
                             barrier-based, at most 12 wavefronts per CU and

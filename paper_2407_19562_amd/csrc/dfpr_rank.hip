@@ -1500,20 +1500,24 @@ __global__ void k_sum(int32_t n, const T *R, double *out) {
   if (lane_id() == 0) atomicAdd(out, s);
 }
 
-// Renormalisation of fp32 ranks: adds (1 - sum) / n to every rank, so that
-// they sum to 1, and recomputes the contributions.  The missing mass is
-// mostly the update's own truncation (every affected vertex within tau of
-// the fixed point, errors of one sign), so a uniform shift keeps each rank
-// within that error; scaling by 1 / sum would move the largest ranks by
-// R_v * (sum - 1) instead (2^22 R-MAT, lock-free fp32: the top rank moved by
-// 1.8e-9, 3e-6 of its value).
+// Renormalisation of fp32 ranks: scales the ranks by 1 / sum and recomputes
+// the contributions, but only when |1 - sum| exceeds `guard` (n * tau).  A
+// converged update misses up to about n * tau of mass by its own
+// truncation (every affected vertex within tau of the fixed point, errors
+// of one sign); rescaling that would move the largest ranks by
+// R_v * (sum - 1) (2^22 R-MAT, lock-free fp32: the top rank by 1.8e-9, 3e-6
+// of its value), and shifting every rank by (1 - sum) / n made small graphs,
+// whose error lies along the ranks themselves, worse.  Drift beyond it
+// (fp32 rounding accumulated over many updates) is rescaled.
 template <typename T>
-__global__ void k_shift(int32_t n, const int32_t *out_deg, const double *sum,
-                        T *R, T *C) {
-  const double d = (1.0 - *sum) / (double)n;
+__global__ void k_scale(int32_t n, const int32_t *out_deg, const double *sum,
+                        double guard, T *R, T *C) {
+  const double sm = *sum;
+  if (fabs(1.0 - sm) <= guard) return;
+  const double f = 1.0 / sm;
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
        v += (int64_t)gridDim.x * blockDim.x) {
-    const double r = (double)R[v] + d;
+    const double r = (double)R[v] * f;
     R[v] = (T)r;
     C[v] = (T)(r / (double)(out_deg[v] + 1));
   }
@@ -2564,8 +2568,9 @@ int renormalize(dfpr_graph *g) {
   DFPR_HIP(hipMemsetAsync(&g->ctl->sum, 0, sizeof(double), s));
   k_sum<T><<<grid_for(g->n, g->cu_count), 256, 0, s>>>(g->n, (const T *)g->R[g->cur],
                                                        &g->ctl->sum);
-  k_shift<T><<<grid_for(g->n, g->cu_count), 256, 0, s>>>(
-      g->n, g->out.deg, &g->ctl->sum, (T *)g->R[g->cur], (T *)g->C[g->cur]);
+  k_scale<T><<<grid_for(g->n, g->cu_count), 256, 0, s>>>(
+      g->n, g->out.deg, &g->ctl->sum, (double)g->n * g->p.tol, (T *)g->R[g->cur],
+      (T *)g->C[g->cur]);
   DFPR_HIP(hipGetLastError());
   return DFPR_OK;
 }

@@ -434,6 +434,29 @@ def test_graph_replay_matches_launches(D, O, kind):
         assert err64(Rr, ref) < FP64_TOL
 
 
+def test_renormalisation_rescales_drift_only(D, O):
+    # fp32 renormalisation: an update whose ranks sum to 1 up to its own
+    # truncation (n * tau) is left as it is, bit for bit (the barrier-based
+    # scheme is deterministic); ranks that start 0.1% too high everywhere
+    # keep that drift on the unaffected vertices, and it is rescaled away
+    say("renormalisation")
+    n, s, d, R0 = base_graph(O, "rmat_small")
+    b = inputs.batches(n, s, d, 1, 1001, frac=1e-3)[0]
+    out = {}
+    for scale in (1.0, 1.001):
+        for renorm in (0, 1):
+            with graph(D, n, s, d, mode=D.DFPR_SYNC, precision=32, renormalize=renorm) as g:
+                g.set_ranks(R0 * scale)
+                g.apply(b)
+                rc, st = g.update()
+                assert rc == D.DFPR_OK and st.converged
+                out[scale, renorm] = g.ranks()
+    assert np.array_equal(out[1.0, 0], out[1.0, 1])
+    assert abs(out[1.0, 1].sum() - 1.0) < n * 1e-10
+    assert abs(out[1.001, 0].sum() - 1.0) > 1e-5
+    assert abs(out[1.001, 1].sum() - 1.0) < 1e-6
+
+
 @pytest.mark.parametrize("mode,kahan", [("sync", 0), ("sync", 8), ("sync", 1 << 30),
                                         ("async", 0)])
 def test_df_fp32_matches_oracle(D, O, mode, kahan):
