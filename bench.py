@@ -711,6 +711,7 @@ def batched(args, torch, dfpr, inputs):
             # every graph against its own oracle fixed point, both launches
             worst = {"batched": 0.0, "sequential": 0.0}
             ok = True
+            missed = []   # graphs outside their bar: which launch, and how far
             for g_i, (kind, n, s, d) in enumerate(gl):
                 b = inputs.batches(n, s, d, 1, seed=5000 + g_i, frac=0.01)[0]
                 ref = oracle_ranks(n, *oracle_graph(n, s, d, [[b]]))
@@ -720,9 +721,13 @@ def batched(args, torch, dfpr, inputs):
                     if prec == 32:
                         worst[key + "_rel"] = max(worst.get(key + "_rel", 0.0), e["rel_linf"])
                     ok = ok and e["ok"]
+                    if not e["ok"]:
+                        missed.append({"graph": g_i, "kind": kind, "n": n, "edges": int(s.size),
+                                       "launch": key, "max_rank": float(ref.max()),
+                                       **{k: v for k, v in e.items() if k != "bar"}})
             err = {"error_vs_oracle": {"max_over_graphs_" + k: v for k, v in worst.items()},
                    "error_bar": "abs 1e-9" if prec == 64 else "rel 1e-6 or abs 1e-9",
-                   "all_ok": ok}
+                   "all_ok": ok, "graphs_outside_bar": missed}
         out[f"fp{prec}"] = {"batched_ms": t_batched, "sequential_ms": t_seq,
                             "speedup": t_seq / t_batched,
                             "edges_gathered": edges,
